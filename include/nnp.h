@@ -1,0 +1,229 @@
+/*
+ * nnp.h -- C ABI of an MI355X (gfx950) library that evaluates a descriptor-based
+ * neural network potential (NNP) and its forces, for the ML atoms of a
+ * molecular-dynamics system, on a caller's HIP stream.
+ *
+ * The operation is the per-step ML/MM force contract of Muellender, Hess and
+ * Lindahl, "Enabling Biomolecular Simulations with Neural Network Potentials in
+ * GROMACS" (arXiv 2604.21441):
+ *   - the NNP supplies the energy E_ML of an index group of atoms (Theory,
+ *     eq. 1) and the forces F_i = -grad_i E_ML on those atoms (eq. 2);
+ *   - its inputs are atomic numbers, positions, the box and periodicity, the
+ *     index group, and optionally MM positions and charges (Methods, "The
+ *     nnpot Interface"); with MM charges the model may also put forces on MM
+ *     atoms (same passage, electrostatic embedding).
+ * The model is an ANI-family network (the family the paper runs and
+ * benchmarks): radial and modified-angular symmetry functions feed one
+ * multilayer perceptron per element; E = sum_i e_i.  Forces come from a
+ * hand-written adjoint (network backward, descriptor backward, FP64 scatter).
+ *
+ * Units: Angstrom, eV, elementary charge; forces in eV/Angstrom.
+ * Arrays named *_host live in host memory; every other array pointer is a
+ * DEVICE pointer (hipMalloc'd or a torch CUDA tensor), owned by the caller.
+ * The library owns its weights and its workspace (sized by nnp_reserve).
+ *
+ * Error behaviour: every entry point returns an nnp_status.  Argument errors
+ * (bad sizes, species not in the table, a box too small for the cutoff, a size
+ * beyond the reserved capacity) are detected on the host before any work is
+ * queued and leave the outputs untouched.  Conditions only the device can see
+ * (a neighbour list overflowing its capacity, non-finite positions or energy)
+ * set a device status word that nnp_get_status reads.  nnp_last_error returns
+ * a human-readable message for the last failing call on the calling thread.
+ *
+ * Thread safety: a model may be used by one host thread at a time; calls on
+ * one model are ordered on the stream they are given.  nnp_compute and
+ * nnp_compute_batch never allocate, never synchronise the host and never call
+ * hipDeviceSynchronize once the model has been reserved and its topology seen,
+ * so they can be captured into a HIP graph.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnp_model nnp_model; /* opaque */
+
+typedef enum {
+  NNP_OK = 0,
+  NNP_EINVAL = -1,     /* bad argument or unsupported configuration            */
+  NNP_ESPECIES = -2,   /* an atomic number is not in the model's species table  */
+  NNP_EBOX = -3,       /* a box length is not larger than twice the cutoff      */
+  NNP_ECAPACITY = -4,  /* a size exceeds what nnp_reserve provided, or (device
+                          status) a neighbour list overflowed its capacity      */
+  NNP_EHIP = -5,       /* a HIP runtime call failed                              */
+  NNP_ESTATE = -6,     /* call made in the wrong state (e.g. before reserve)     */
+  NNP_ENONFINITE = -7  /* (device status) non-finite position or energy          */
+} nnp_status;
+
+typedef enum { NNP_FP32 = 0, NNP_BF16 = 1 } nnp_precision;
+
+/*
+ * Model hyper-parameters (host struct, copied by nnp_create).
+ *
+ * Descriptor of atom i (ANI form; the paper cites ANI as its descriptor-based
+ * family, Introduction and Methods):
+ *   radial   G[s][k]   = sum_{j: species s, r_ij < rc_rad}
+ *                          exp(-eta_rad (r_ij - rad_shift[k])^2) fc(r_ij; rc_rad)
+ *   angular  G[p][m][n] = 2^(1-zeta) sum_{j<k in species pair p, r_ij, r_ik < rc_ang}
+ *                          (1 + cos(theta' - ang_sect[n]))^zeta
+ *                          exp(-eta_ang ((r_ij + r_ik)/2 - ang_shift[m])^2)
+ *                          fc(r_ij; rc_ang) fc(r_ik; rc_ang),
+ *            theta' = arccos(0.95 cos theta_ijk)
+ *   fc(r; R) = 0.5 cos(pi r / R) + 0.5 for r < R, else 0.
+ * Row layout: radial block [s][k], then angular block [p][m][n], species pairs
+ * p ordered lexicographically over (a <= b) of the species table; with
+ * extra_inputs = 1 the MM potential phi_i = ke_coulomb sum_j q_j fc(r_ij;
+ * mm_cutoff) / r_ij is appended as the last input.
+ * Network per species: h_l = CELU_alpha(W_l h_{l-1} + b_l) for the hidden
+ * layers, e_i = W_L h_{L-1} + b_L (linear output).
+ * Supported: 1..4 species; 16 radial shifts, 8 angular shifts, 4 angle
+ * sections; widths {128,160,128,96,1} (water model) or {384(+1),256,192,160,1}
+ * (H/C/N/O model); n_members >= 1 networks averaged (an ensemble sharing one
+ * descriptor).
+ */
+typedef struct {
+  int32_t n_species;
+  const int32_t* atomic_numbers_host; /* [n_species], strictly ascending          */
+  float rc_rad, rc_ang;               /* cutoffs, rc_ang <= rc_rad                 */
+  float eta_rad, eta_ang, zeta;
+  int32_t n_rad_shift, n_ang_shift, n_ang_sect; /* must be 16, 8, 4                 */
+  const float* rad_shift_host;        /* [n_rad_shift]                             */
+  const float* ang_shift_host;        /* [n_ang_shift]                             */
+  const float* ang_sect_host;         /* [n_ang_sect] section centres (radians)    */
+  int32_t n_layers;                   /* number of entries in widths (5)           */
+  const int32_t* widths_host;         /* [n_layers]; widths[0] = descriptor length
+                                         + extra_inputs, widths[n_layers-1] = 1    */
+  float celu_alpha;
+  int32_t extra_inputs;               /* 0, or 1 for the MM potential channel      */
+  float mm_cutoff;                    /* cutoff of the MM potential channel        */
+  double ke_coulomb;                  /* Coulomb constant, eV*A/e^2                */
+  int32_t n_members;                  /* ensemble size (>= 1)                      */
+} nnp_config;
+
+/*
+ * Create a model.  weights_host (FP32, host) holds, in order: for each
+ * ensemble member, for each species (table order), for each layer: W
+ * (out x in, row-major) then b (out).  If weights_host is NULL the weights
+ * are drawn from `seed`: value t of the draw uses uniforms u = top 53 bits of
+ * SplitMix64 outputs 2t and 2t+1 (Steele, Lea & Flood 2014) through Box-Muller
+ * z = sqrt(-2 ln(1-u0)) cos(2 pi u1); W ~ N(0, 2/(fan_in+fan_out)),
+ * b ~ N(0, 0.01); each value rounded once to FP32.
+ * prec selects the network arithmetic: NNP_FP32 (FP32 matrix cores) or
+ * NNP_BF16 (BF16 operands, FP32 accumulation).  Descriptors and their
+ * derivatives are FP32 in both forms; energies and force accumulation FP64.
+ * Uses the current HIP device; allocates the device weights.  *out is set
+ * on success.
+ */
+nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights_host,
+                      nnp_precision prec, nnp_model** out);
+
+/*
+ * Allocate the workspace for up to max_atoms atoms (all atoms of a call,
+ * NNP or not), max_systems systems in one batched call, max_mm MM charges,
+ * and per-atom neighbour-list capacities max_rad_nbr (within rc_rad) and
+ * max_ang_nbr (within rc_ang); 0 selects the defaults 128 and 48.  May be
+ * called again to grow or shrink; synchronises the device.  All device
+ * allocation of the model happens here and in nnp_create.
+ */
+nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int32_t max_mm,
+                       int32_t max_rad_nbr, int32_t max_ang_nbr);
+
+/*
+ * Energy and forces of one system, queued on `stream`.
+ *   n_atoms         number of atoms of the system (rows of pos and forces)
+ *   pos             [n_atoms][3] FP32 positions (need not be wrapped)
+ *   Z_host          [n_atoms] atomic numbers; only NNP atoms need to be in
+ *                   the species table.  NULL reuses the previous call's
+ *                   topology (Z, index group) unchanged.
+ *   box_host        [3] orthorhombic box lengths (periodic in all three
+ *                   directions, minimum image; each length must exceed
+ *                   2*rc_rad and, with the MM channel, 2*mm_cutoff), or NULL
+ *                   for an open (non-periodic) system.
+ *   n_nnp, nnp_idx_host  the index group: NNP atoms are nnp_idx_host[0..n_nnp)
+ *                   (distinct, in [0, n_atoms)); nnp_idx_host NULL with
+ *                   n_nnp == n_atoms means all atoms.
+ *   n_mm, mm_pos, mm_q  MM point charges ([n_mm][3] FP32 positions, [n_mm]
+ *                   FP32 charges); required iff the model has extra_inputs.
+ *   energy          [1] FP64 output, E_ML
+ *   forces          [n_atoms][3] FP64 output, -dE/dx; rows of non-NNP atoms
+ *                   receive zero
+ *   mm_forces       [n_mm][3] FP64 output (-dE/dy for MM atoms) or NULL
+ *   accumulate      0: outputs are overwritten; 1: results are added to them
+ * Returns after queueing; the outputs are valid when the stream reaches that
+ * point.  A topology change (Z or index group differing from the previous
+ * call) is uploaded from host memory inside the call.
+ */
+nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
+                       const float* box_host, int32_t n_nnp, const int32_t* nnp_idx_host,
+                       int32_t n_mm, const float* mm_pos, const float* mm_q, double* energy,
+                       double* forces, double* mm_forces, int32_t accumulate, hipStream_t stream);
+
+/*
+ * Energies and forces of n_sys independent open (non-periodic) systems packed
+ * back to back: system s owns atoms [atom_offsets_host[s], atom_offsets_host[s+1]).
+ * All atoms are NNP atoms.  energies [n_sys] FP64, forces [total][3] FP64, both
+ * overwritten.  Z_host NULL reuses the previous batched call's topology.
+ * One neighbour search, one descriptor launch, one grouped network launch and
+ * one adjoint launch cover all systems.
+ */
+nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host,
+                             const float* pos, const int32_t* Z_host, double* energies,
+                             double* forces, hipStream_t stream);
+
+/*
+ * Synchronise `stream` and report the device status word of the calls made
+ * since the previous nnp_get_status: NNP_OK, NNP_ECAPACITY (a neighbour list
+ * overflowed; results are incomplete -- nnp_reserve larger capacities) or
+ * NNP_ENONFINITE.  Clears the word.
+ */
+nnp_status nnp_get_status(nnp_model* m, hipStream_t stream);
+
+/* Intermediate buffers of the last call, for inspection and tests. */
+typedef enum {
+  NNP_BUF_PERM = 0,       /* int32 [n_nnp]: sorted slot -> NNP-local atom (stable
+                             counting sort by key = species * n_bins + bin)      */
+  NNP_BUF_KEY = 1,        /* int32 [n_nnp]: key of each NNP-local atom           */
+  NNP_BUF_BIN_START = 2,  /* int32 [n_species * n_bins + 1]                      */
+  NNP_BUF_NBR_COUNT = 3,  /* int32 [n_nnp][2]: radial, angular neighbour counts
+                             per sorted slot                                     */
+  NNP_BUF_NBR_RAD = 4,    /* int32 [n_nnp][max_rad_nbr]: radial neighbours (sorted
+                             slots), grouped by species                          */
+  NNP_BUF_NBR_ANG = 5,    /* int32 [n_nnp][max_ang_nbr]: angular neighbours       */
+  NNP_BUF_DESCRIPTOR = 6, /* float [n_nnp][row stride] per sorted slot           */
+  NNP_BUF_ATOM_ENERGY = 7,/* float [n_nnp] atomic energies per sorted slot        */
+  NNP_BUF_DEDX = 8,       /* float [n_nnp][row stride] dE/d(descriptor) per slot  */
+  NNP_BUF_GRID = 9        /* int32 [4]: n_bins, cells per dimension x, y, z      */
+} nnp_buffer;
+
+/*
+ * Copy an intermediate buffer to host memory (synchronises `stream`).
+ * *elems receives the element count; at most capacity_bytes are written.
+ * *row_stride receives the row length of 2-D buffers (elements), else 1.
+ */
+nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_t capacity_bytes,
+                           int64_t* elems, int32_t* row_stride, hipStream_t stream);
+
+/* Free the model, its weights and its workspace. */
+void nnp_destroy(nnp_model* m);
+
+/* Static description of a status code. */
+const char* nnp_status_string(nnp_status s);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* nnp_last_error(void);
+
+/* Library version as "major.minor.patch". */
+const char* nnp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

@@ -1,0 +1,522 @@
+// C ABI entry points: model lifecycle, argument validation, the topology
+// cache, and the per-call sequence of stage launches on the caller's stream.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nnp_internal.h"
+
+namespace nnp {
+
+static thread_local std::string g_last_error;
+
+nnp_status set_error(nnp_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+nnp_status hip_error(hipError_t e, const char* what) {
+  return set_error(NNP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+#define HIP_TRY(expr, what)                      \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_workspace(nnp_model* m) {
+  dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_key); dfree(m->d_bin_count);
+  dfree(m->d_bin_start); dfree(m->d_cursor); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
+  dfree(m->d_slot_atom); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
+  dfree(m->d_ang_off); dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
+  if (m->h_stage) (void)hipHostFree(m->h_stage);
+  m->h_stage = nullptr;
+  m->reserved = false;
+  m->topo_mode = -1;
+}
+
+int descriptor_length(int S) { return kRadShifts * S + kAngShifts * kAngSects * (S * (S + 1) / 2); }
+
+// Upload the host topology through the pinned staging buffer.
+nnp_status upload_ints(nnp_model* m, int* dst, const int* src, int n, hipStream_t st) {
+  if (n <= 0) return NNP_OK;
+  std::memcpy(m->h_stage, src, sizeof(int) * (size_t)n);
+  HIP_TRY(hipMemcpyAsync(dst, m->h_stage, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, st), "topology upload");
+  HIP_TRY(hipStreamSynchronize(st), "topology upload");
+  return NNP_OK;
+}
+
+nnp_status species_of(const nnp_model* m, int z, int* out) {
+  for (int s = 0; s < m->S; ++s)
+    if (m->species[s] == z) {
+      *out = s;
+      return NNP_OK;
+    }
+  return set_error(NNP_ESPECIES, "atomic number " + std::to_string(z) + " is not in the species table");
+}
+
+}  // namespace
+}  // namespace nnp
+
+using namespace nnp;
+
+extern "C" {
+
+const char* nnp_version(void) { return "0.1.0"; }
+
+const char* nnp_last_error(void) { return g_last_error.c_str(); }
+
+const char* nnp_status_string(nnp_status s) {
+  switch (s) {
+    case NNP_OK: return "ok";
+    case NNP_EINVAL: return "invalid argument";
+    case NNP_ESPECIES: return "atomic number not in the species table";
+    case NNP_EBOX: return "box length not larger than twice the cutoff";
+    case NNP_ECAPACITY: return "capacity exceeded";
+    case NNP_EHIP: return "HIP runtime error";
+    case NNP_ESTATE: return "invalid call sequence";
+    case NNP_ENONFINITE: return "non-finite position or energy";
+  }
+  return "unknown status";
+}
+
+nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights_host, nnp_precision prec,
+                      nnp_model** out) {
+  if (!cfg || !out) return set_error(NNP_EINVAL, "null argument");
+  *out = nullptr;
+  const int S = cfg->n_species;
+  if (S < 1 || S > kMaxSpecies || !cfg->atomic_numbers_host)
+    return set_error(NNP_EINVAL, "n_species must be 1..4 with an atomic number table");
+  for (int s = 1; s < S; ++s)
+    if (cfg->atomic_numbers_host[s] <= cfg->atomic_numbers_host[s - 1])
+      return set_error(NNP_EINVAL, "atomic numbers must be strictly ascending");
+  if (cfg->n_rad_shift != kRadShifts || cfg->n_ang_shift != kAngShifts || cfg->n_ang_sect != kAngSects ||
+      !cfg->rad_shift_host || !cfg->ang_shift_host || !cfg->ang_sect_host)
+    return set_error(NNP_EINVAL, "the descriptor needs 16 radial shifts, 8 angular shifts and 4 sections");
+  if (!(cfg->rc_rad > 0.f) || !(cfg->rc_ang > 0.f) || cfg->rc_ang > cfg->rc_rad || !(cfg->eta_rad > 0.f) ||
+      !(cfg->eta_ang > 0.f) || !(cfg->zeta > 0.f) || !(cfg->celu_alpha > 0.f))
+    return set_error(NNP_EINVAL, "cutoffs, widths and exponents must be positive, rc_ang <= rc_rad");
+  if (cfg->extra_inputs != 0 && cfg->extra_inputs != 1) return set_error(NNP_EINVAL, "extra_inputs must be 0 or 1");
+  if (cfg->extra_inputs && !(cfg->mm_cutoff > 0.f)) return set_error(NNP_EINVAL, "mm_cutoff must be positive");
+  if (cfg->n_members < 1) return set_error(NNP_EINVAL, "n_members must be >= 1");
+  if (cfg->n_layers != 5 || !cfg->widths_host) return set_error(NNP_EINVAL, "networks have 5 widths (4 layers)");
+  if (prec != NNP_FP32 && prec != NNP_BF16) return set_error(NNP_EINVAL, "unknown precision");
+  const int D = descriptor_length(S);
+  std::vector<int> w(cfg->widths_host, cfg->widths_host + 5);
+  if (w[0] != D + cfg->extra_inputs || w[4] != 1)
+    return set_error(NNP_EINVAL, "widths[0] must equal the descriptor length plus extra_inputs, widths[4] = 1");
+  int kind = -1, stride = 0;
+  if (w[1] == 160 && w[2] == 128 && w[3] == 96 && D == 128 && cfg->extra_inputs == 0) {
+    kind = 0; stride = 128;
+  } else if (w[1] == 256 && w[2] == 192 && w[3] == 160 && D == 384) {
+    kind = cfg->extra_inputs ? 2 : 1;
+    stride = cfg->extra_inputs ? 416 : 384;
+  }
+  if (kind < 0)
+    return set_error(NNP_EINVAL,
+                     "supported networks: 2 species 128-160-128-96-1, 4 species 384(+1)-256-192-160-1");
+
+  nnp_model* m = new (std::nothrow) nnp_model();
+  if (!m) return set_error(NNP_EINVAL, "out of host memory");
+  (void)hipGetDevice(&m->device);
+  m->prec = prec;
+  m->S = S;
+  m->P = S * (S + 1) / 2;
+  m->D = D;
+  m->extra = cfg->extra_inputs;
+  m->Din = D + cfg->extra_inputs;
+  m->stride = stride;
+  m->n_members = cfg->n_members;
+  m->species.assign(cfg->atomic_numbers_host, cfg->atomic_numbers_host + S);
+  m->widths = w;
+  m->celu_alpha = cfg->celu_alpha;
+  m->net_kind = kind;
+
+  DescParams& p = m->dp;
+  p.rc_rad = cfg->rc_rad;
+  p.rc_ang = cfg->rc_ang;
+  p.eta_rad = cfg->eta_rad;
+  p.eta_ang = cfg->eta_ang;
+  p.zeta = cfg->zeta;
+  p.ang_pref = (float)std::pow(2.0, 1.0 - (double)cfg->zeta);
+  for (int k = 0; k < kRadShifts; ++k) p.rad_shift[k] = cfg->rad_shift_host[k];
+  for (int k = 0; k < kAngShifts; ++k) p.ang_shift[k] = cfg->ang_shift_host[k];
+  for (int k = 0; k < kAngSects; ++k) {
+    p.cos_sect[k] = (float)std::cos((double)cfg->ang_sect_host[k]);
+    p.sin_sect[k] = (float)std::sin((double)cfg->ang_sect_host[k]);
+  }
+  p.mm_cutoff = cfg->mm_cutoff;
+  p.ke = (float)cfg->ke_coulomb;
+  p.S = S;
+  p.P = m->P;
+  p.D = D;
+  p.stride = stride;
+  p.extra = cfg->extra_inputs;
+  int q = 0;
+  for (int a = 0; a < S; ++a)
+    for (int b = a; b < S; ++b) {
+      p.pair_a[q] = a;
+      p.pair_b[q] = b;
+      ++q;
+    }
+
+  // weights
+  size_t per_species = 0;
+  for (int l = 0; l < 4; ++l) per_species += (size_t)w[l] * w[l + 1] + w[l + 1];
+  const size_t total = per_species * S * m->n_members;
+  if (weights_host) {
+    m->w_host.assign(weights_host, weights_host + total);
+  } else {
+    draw_weights(seed, w, S, m->n_members, m->w_host);
+  }
+  std::vector<uint8_t> mat;
+  std::vector<float> vec;
+  pack_weights(*m, mat, vec, m->mat_per_species, m->vec_per_species);
+  hipError_t e = hipMalloc(&m->d_wmat, mat.size());
+  if (e == hipSuccess) e = hipMemcpy(m->d_wmat, mat.data(), mat.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = dalloc(&m->d_wvec, vec.size());
+  if (e == hipSuccess) e = hipMemcpy(m->d_wvec, vec.data(), vec.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = dalloc(&m->d_status, 1);
+  if (e == hipSuccess) e = hipMemset(m->d_status, 0, sizeof(int));
+  if (e != hipSuccess) {
+    nnp_destroy(m);
+    return hip_error(e, "nnp_create");
+  }
+  *out = m;
+  return NNP_OK;
+}
+
+nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int32_t max_mm, int32_t max_rad_nbr,
+                       int32_t max_ang_nbr) {
+  if (!m) return set_error(NNP_EINVAL, "null model");
+  if (max_atoms < 1 || max_systems < 1 || max_mm < 0 || max_rad_nbr < 0 || max_ang_nbr < 0)
+    return set_error(NNP_EINVAL, "capacities must be positive");
+  HIP_TRY(hipDeviceSynchronize(), "nnp_reserve");
+  free_workspace(m);
+  m->max_atoms = max_atoms;
+  m->max_sys = max_systems;
+  m->max_mm = max_mm;
+  m->max_rad = max_rad_nbr ? max_rad_nbr : 128;
+  m->max_ang = max_ang_nbr ? max_ang_nbr : 48;
+  int cells_cap = max_atoms > 64 ? max_atoms : 64;
+  int per_species_bins = cells_cap > max_systems ? cells_cap : max_systems;
+  m->max_bins = m->S * per_species_bins;
+  const size_t n = (size_t)max_atoms;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chk(dalloc(&m->d_idx, n));
+  chk(dalloc(&m->d_sigma, n));
+  chk(dalloc(&m->d_sys, n));
+  chk(dalloc(&m->d_key, n));
+  chk(dalloc(&m->d_perm, n));
+  chk(dalloc(&m->d_tmp, n));
+  chk(dalloc(&m->d_slot_atom, n));
+  chk(dalloc(&m->d_spos, n));
+  chk(dalloc(&m->d_bin_count, (size_t)m->max_bins));
+  chk(dalloc(&m->d_cursor, (size_t)m->max_bins));
+  chk(dalloc(&m->d_bin_start, (size_t)m->max_bins + 1));
+  chk(dalloc(&m->d_nbr_rad, n * m->max_rad));
+  chk(dalloc(&m->d_nbr_ang, n * m->max_ang));
+  chk(dalloc(&m->d_rad_off, n * (m->S + 1)));
+  chk(dalloc(&m->d_ang_off, n * (m->S + 1)));
+  chk(dalloc(&m->d_x, n * m->stride));
+  chk(dalloc(&m->d_g, n * m->stride));
+  chk(dalloc(&m->d_e, n));
+  chk(dalloc(&m->d_phi, n));
+  if (e == hipSuccess) e = hipMemset(m->d_x, 0, n * m->stride * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->d_g, 0, n * m->stride * sizeof(float));
+  if (e == hipSuccess) {
+    size_t stage = 3 * n + 8;
+    if ((size_t)max_systems + 1 > stage) stage = (size_t)max_systems + 1;
+    e = hipHostMalloc(reinterpret_cast<void**>(&m->h_stage), stage * sizeof(int), hipHostMallocDefault);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_workspace(m);
+    return hip_error(e, "nnp_reserve");
+  }
+  m->reserved = true;
+  return NNP_OK;
+}
+
+namespace {
+
+// Box checks and the cell grid of a periodic call.
+nnp_status setup_periodic(nnp_model* m, const float* box) {
+  Geometry& g = m->geo;
+  g.periodic = 1;
+  const float rc = m->dp.rc_rad;
+  long long cells = 1;
+  for (int k = 0; k < 3; ++k) {
+    float L = box[k];
+    if (!(std::isfinite(L)) || !(L > 2.f * rc))
+      return set_error(NNP_EBOX, "box length " + std::to_string(L) + " must exceed twice the cutoff");
+    if (m->extra && !(L > 2.f * m->dp.mm_cutoff))
+      return set_error(NNP_EBOX, "box length must exceed twice the MM cutoff");
+    g.box[k] = L;
+    g.inv_box[k] = 1.0f / L;
+    float q = std::floor(L / rc);
+    g.nc[k] = q < 1.f ? 1 : (int)q;
+    cells *= g.nc[k];
+  }
+  // keep the grid within the reserved bins (larger cells stay correct)
+  const long long cap = m->max_bins / m->S;
+  while (cells > cap) {
+    int k = 0;
+    for (int d = 1; d < 3; ++d)
+      if (g.nc[d] > g.nc[k]) k = d;
+    g.nc[k] = g.nc[k] > 1 ? g.nc[k] / 2 : 1;
+    cells = (long long)g.nc[0] * g.nc[1] * g.nc[2];
+  }
+  for (int k = 0; k < 3; ++k) g.cell_scale[k] = (float)g.nc[k] * g.inv_box[k];
+  g.n_bins = (int)cells;
+  return NNP_OK;
+}
+
+nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float* mm_pos, const float* mm_q,
+                    double* energies, int n_sys, double* forces, double* mm_forces, int accumulate,
+                    hipStream_t st) {
+  hipError_t e;
+  m->last_n = n;
+  if ((e = launch_cells(*m, pos, n, st)) != hipSuccess) return hip_error(e, "cell list");
+  if ((e = launch_neighbours(*m, n, st)) != hipSuccess) return hip_error(e, "neighbours");
+  if ((e = launch_descriptor_fwd(*m, n, st)) != hipSuccess) return hip_error(e, "descriptor");
+  if (m->extra) {
+    if ((e = launch_mm_fwd(*m, n, n_mm, mm_pos, mm_q, st)) != hipSuccess) return hip_error(e, "mm channel");
+  }
+  if ((e = launch_mlp(*m, n, st)) != hipSuccess) return hip_error(e, "network");
+  if ((e = launch_energy(*m, n_sys, energies, accumulate, st)) != hipSuccess) return hip_error(e, "energy");
+  if ((e = launch_descriptor_bwd(*m, n, forces, st)) != hipSuccess) return hip_error(e, "descriptor adjoint");
+  if (m->extra) {
+    if ((e = launch_mm_bwd(*m, n, n_mm, mm_pos, mm_q, forces, mm_forces, st)) != hipSuccess)
+      return hip_error(e, "mm adjoint");
+  }
+  return NNP_OK;
+}
+
+}  // namespace
+
+nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host, const float* box_host,
+                       int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_mm, const float* mm_pos,
+                       const float* mm_q, double* energy, double* forces, double* mm_forces, int32_t accumulate,
+                       hipStream_t stream) {
+  if (!m) return set_error(NNP_EINVAL, "null model");
+  if (!m->reserved) return set_error(NNP_ESTATE, "nnp_reserve must be called first");
+  if (n_atoms < 0 || n_nnp < 0 || n_nnp > n_atoms) return set_error(NNP_EINVAL, "bad atom counts");
+  if (n_atoms > m->max_atoms)
+    return set_error(NNP_ECAPACITY, "n_atoms exceeds the reserved capacity " + std::to_string(m->max_atoms));
+  if (!energy || (n_atoms > 0 && (!pos || !forces))) return set_error(NNP_EINVAL, "null output or position array");
+  if (m->extra) {
+    if (n_mm < 0 || (n_mm > 0 && (!mm_pos || !mm_q)))
+      return set_error(NNP_EINVAL, "this model needs MM positions and charges");
+    if (n_mm > m->max_mm) return set_error(NNP_ECAPACITY, "n_mm exceeds the reserved capacity");
+  } else if (n_mm != 0) {
+    return set_error(NNP_EINVAL, "MM charges given to a model without the MM input channel");
+  }
+  if (accumulate != 0 && accumulate != 1) return set_error(NNP_EINVAL, "accumulate must be 0 or 1");
+
+  // topology
+  if (Z_host) {
+    bool same = m->topo_mode == 0 && m->topo_n_atoms == n_atoms && m->n_nnp == n_nnp &&
+                std::memcmp(m->topo_Z.data(), Z_host, sizeof(int) * (size_t)n_atoms) == 0;
+    if (same) {
+      if (nnp_idx_host)
+        same = m->topo_idx.size() == (size_t)n_nnp &&
+               std::memcmp(m->topo_idx.data(), nnp_idx_host, sizeof(int) * (size_t)n_nnp) == 0;
+      else
+        same = m->topo_idx.empty();
+    }
+    if (!same) {
+      if (!nnp_idx_host && n_nnp != n_atoms) return set_error(NNP_EINVAL, "nnp_idx is NULL but n_nnp != n_atoms");
+      std::vector<int> idx(n_nnp), sig(n_nnp);
+      std::vector<char> seen(n_atoms, 0);
+      for (int t = 0; t < n_nnp; ++t) {
+        int a = nnp_idx_host ? nnp_idx_host[t] : t;
+        if (a < 0 || a >= n_atoms || seen[a]) return set_error(NNP_EINVAL, "index group entries must be distinct and in range");
+        seen[a] = 1;
+        idx[t] = a;
+        nnp_status s = species_of(m, Z_host[a], &sig[t]);
+        if (s != NNP_OK) return s;
+      }
+      nnp_status s;
+      if ((s = upload_ints(m, m->d_idx, idx.data(), n_nnp, stream)) != NNP_OK) return s;
+      if ((s = upload_ints(m, m->d_sigma, sig.data(), n_nnp, stream)) != NNP_OK) return s;
+      std::vector<int> zeros(n_nnp, 0);  // an open single system is system 0
+      if ((s = upload_ints(m, m->d_sys, zeros.data(), n_nnp, stream)) != NNP_OK) return s;
+      m->topo_mode = 0;
+      m->topo_n_atoms = n_atoms;
+      m->n_nnp = n_nnp;
+      m->topo_Z.assign(Z_host, Z_host + n_atoms);
+      if (nnp_idx_host) m->topo_idx.assign(nnp_idx_host, nnp_idx_host + n_nnp);
+      else m->topo_idx.clear();
+    }
+  } else if (m->topo_mode != 0 || m->topo_n_atoms != n_atoms || m->n_nnp != n_nnp) {
+    return set_error(NNP_ESTATE, "Z_host is NULL but no matching topology was given before");
+  }
+
+  // geometry
+  if (box_host) {
+    nnp_status s = setup_periodic(m, box_host);
+    if (s != NNP_OK) return s;
+  } else {
+    m->geo = Geometry{};
+    m->geo.periodic = 0;
+    m->geo.n_bins = 1;
+    m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
+  }
+  hipError_t e;
+  if (!accumulate) {
+    if ((e = launch_fill_f64(forces, 3 * (int64_t)n_atoms, stream)) != hipSuccess) return hip_error(e, "fill");
+    if (mm_forces && (e = launch_fill_f64(mm_forces, 3 * (int64_t)n_mm, stream)) != hipSuccess)
+      return hip_error(e, "fill");
+  }
+  return run_path(m, n_nnp, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, stream);
+}
+
+nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host, const float* pos,
+                             const int32_t* Z_host, double* energies, double* forces, hipStream_t stream) {
+  if (!m) return set_error(NNP_EINVAL, "null model");
+  if (!m->reserved) return set_error(NNP_ESTATE, "nnp_reserve must be called first");
+  if (m->extra) return set_error(NNP_EINVAL, "batched calls do not take MM charges");
+  if (n_sys < 1 || !atom_offsets_host) return set_error(NNP_EINVAL, "need at least one system and its offsets");
+  if (n_sys > m->max_sys) return set_error(NNP_ECAPACITY, "n_sys exceeds the reserved capacity");
+  if (atom_offsets_host[0] != 0) return set_error(NNP_EINVAL, "atom_offsets[0] must be 0");
+  for (int s = 0; s < n_sys; ++s)
+    if (atom_offsets_host[s + 1] < atom_offsets_host[s]) return set_error(NNP_EINVAL, "offsets must be non-decreasing");
+  const int n = atom_offsets_host[n_sys];
+  if (n > m->max_atoms) return set_error(NNP_ECAPACITY, "total atoms exceed the reserved capacity");
+  if (!energies || (n > 0 && (!pos || !forces))) return set_error(NNP_EINVAL, "null output or position array");
+
+  if (Z_host) {
+    bool same = m->topo_mode == 1 && m->topo_n_atoms == n && (int)m->topo_offsets.size() == n_sys + 1 &&
+                std::memcmp(m->topo_offsets.data(), atom_offsets_host, sizeof(int) * (size_t)(n_sys + 1)) == 0 &&
+                std::memcmp(m->topo_Z.data(), Z_host, sizeof(int) * (size_t)n) == 0;
+    if (!same) {
+      std::vector<int> idx(n), sig(n), sys(n);
+      for (int s = 0; s < n_sys; ++s)
+        for (int a = atom_offsets_host[s]; a < atom_offsets_host[s + 1]; ++a) sys[a] = s;
+      for (int a = 0; a < n; ++a) {
+        idx[a] = a;
+        nnp_status st = species_of(m, Z_host[a], &sig[a]);
+        if (st != NNP_OK) return st;
+      }
+      nnp_status st;
+      if ((st = upload_ints(m, m->d_idx, idx.data(), n, stream)) != NNP_OK) return st;
+      if ((st = upload_ints(m, m->d_sigma, sig.data(), n, stream)) != NNP_OK) return st;
+      if ((st = upload_ints(m, m->d_sys, sys.data(), n, stream)) != NNP_OK) return st;
+      m->topo_mode = 1;
+      m->topo_n_atoms = n;
+      m->n_nnp = n;
+      m->topo_Z.assign(Z_host, Z_host + n);
+      m->topo_offsets.assign(atom_offsets_host, atom_offsets_host + n_sys + 1);
+      m->topo_idx.clear();
+    }
+  } else if (m->topo_mode != 1 || m->topo_n_atoms != n || (int)m->topo_offsets.size() != n_sys + 1) {
+    return set_error(NNP_ESTATE, "Z_host is NULL but no matching batched topology was given before");
+  }
+  m->geo = Geometry{};
+  m->geo.periodic = 0;
+  m->geo.n_bins = n_sys;
+  m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
+  if (m->S * n_sys > m->max_bins) return set_error(NNP_ECAPACITY, "too many systems for the reserved bins");
+  hipError_t e;
+  if ((e = launch_fill_f64(forces, 3 * (int64_t)n, stream)) != hipSuccess) return hip_error(e, "fill");
+  return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, stream);
+}
+
+nnp_status nnp_get_status(nnp_model* m, hipStream_t stream) {
+  if (!m || !m->d_status) return set_error(NNP_EINVAL, "null model");
+  HIP_TRY(hipStreamSynchronize(stream), "nnp_get_status");
+  int h = 0;
+  HIP_TRY(hipMemcpy(&h, m->d_status, sizeof(int), hipMemcpyDeviceToHost), "nnp_get_status");
+  HIP_TRY(hipMemset(m->d_status, 0, sizeof(int)), "nnp_get_status");
+  if (h & kStatusCapacity) return set_error(NNP_ECAPACITY, "a neighbour list overflowed its capacity");
+  if (h & kStatusNonFinite) return set_error(NNP_ENONFINITE, "non-finite position or energy");
+  return NNP_OK;
+}
+
+nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_t capacity_bytes, int64_t* elems,
+                           int32_t* row_stride, hipStream_t stream) {
+  if (!m || !elems || !row_stride) return set_error(NNP_EINVAL, "null argument");
+  if (!m->reserved) return set_error(NNP_ESTATE, "nothing computed yet");
+  HIP_TRY(hipStreamSynchronize(stream), "nnp_read_buffer");
+  const int n = m->last_n;
+  const void* src = nullptr;
+  size_t esz = 4;
+  int64_t count = 0;
+  int32_t stride = 1;
+  std::vector<int> tmp;
+  switch (which) {
+    case NNP_BUF_PERM: src = m->d_perm; count = n; break;
+    case NNP_BUF_KEY: src = m->d_key; count = n; break;
+    case NNP_BUF_BIN_START: src = m->d_bin_start; count = (int64_t)m->S * m->geo.n_bins + 1; break;
+    case NNP_BUF_NBR_RAD: src = m->d_nbr_rad; count = (int64_t)n * m->max_rad; stride = m->max_rad; break;
+    case NNP_BUF_NBR_ANG: src = m->d_nbr_ang; count = (int64_t)n * m->max_ang; stride = m->max_ang; break;
+    case NNP_BUF_DESCRIPTOR: src = m->d_x; count = (int64_t)n * m->stride; stride = m->stride; break;
+    case NNP_BUF_ATOM_ENERGY: src = m->d_e; count = n; break;
+    case NNP_BUF_DEDX: src = m->d_g; count = (int64_t)n * m->stride; stride = m->stride; break;
+    case NNP_BUF_NBR_COUNT: {
+      std::vector<int> ro((size_t)n * (m->S + 1)), ao((size_t)n * (m->S + 1));
+      if (n > 0) {
+        HIP_TRY(hipMemcpy(ro.data(), m->d_rad_off, ro.size() * 4, hipMemcpyDeviceToHost), "read");
+        HIP_TRY(hipMemcpy(ao.data(), m->d_ang_off, ao.size() * 4, hipMemcpyDeviceToHost), "read");
+      }
+      tmp.resize((size_t)2 * n);
+      for (int i = 0; i < n; ++i) {
+        tmp[2 * i] = ro[(size_t)i * (m->S + 1) + m->S];
+        tmp[2 * i + 1] = ao[(size_t)i * (m->S + 1) + m->S];
+      }
+      count = 2 * (int64_t)n;
+      stride = 2;
+      break;
+    }
+    case NNP_BUF_GRID: {
+      tmp = {m->geo.n_bins, m->geo.nc[0], m->geo.nc[1], m->geo.nc[2]};
+      count = 4;
+      break;
+    }
+    default: return set_error(NNP_EINVAL, "unknown buffer");
+  }
+  *elems = count;
+  *row_stride = stride;
+  size_t bytes = (size_t)count * esz;
+  if (bytes > capacity_bytes) bytes = capacity_bytes;
+  if (bytes == 0) return NNP_OK;
+  if (!dst_host) return set_error(NNP_EINVAL, "null destination");
+  if (!tmp.empty() || which == NNP_BUF_NBR_COUNT || which == NNP_BUF_GRID) {
+    std::memcpy(dst_host, tmp.data(), bytes);
+  } else {
+    HIP_TRY(hipMemcpy(dst_host, src, bytes, hipMemcpyDeviceToHost), "nnp_read_buffer");
+  }
+  return NNP_OK;
+}
+
+void nnp_destroy(nnp_model* m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  free_workspace(m);
+  if (m->d_wmat) (void)hipFree(m->d_wmat);
+  dfree(m->d_wvec);
+  dfree(m->d_status);
+  delete m;
+}
+
+}  // extern "C"

@@ -1,0 +1,279 @@
+// Cell-list neighbour search: binning, a stable counting sort by
+// key = species * n_bins + bin, and per-atom neighbour lists grouped by
+// species.  A bin is a cell of the periodic box, or a whole system in batched
+// mode (open systems small enough for an all-pairs scan per system).
+//
+// The binning and the distance predicate are integer-exact functions of the
+// FP32 inputs: every operation below is a single IEEE FP32 operation in a
+// fixed order with floating-point contraction disabled, so an FP32 reference
+// that performs the same operations reproduces the bins, the permutation and
+// the neighbour sets bit for bit.
+#include "nnp_internal.h"
+
+namespace nnp {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int* __restrict__ p, int n, int v) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// Bin of one position in the periodic grid.
+__device__ __forceinline__ int cell_of(float x, float y, float z, const Geometry& g) {
+#pragma clang fp contract(off)
+  float c[3] = {x, y, z};
+  int ci[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float t = c[k] * g.inv_box[k];
+    float f = floorf(t);
+    float fl = f * g.box[k];
+    float w = c[k] - fl;
+    float sc = w * g.cell_scale[k];
+    int q = (int)floorf(sc);
+    q = q < 0 ? 0 : q;
+    q = q > g.nc[k] - 1 ? g.nc[k] - 1 : q;
+    ci[k] = q;
+  }
+  return (ci[0] * g.nc[1] + ci[1]) * g.nc[2] + ci[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos, int n,
+                                                  const int* __restrict__ idx,
+                                                  const int* __restrict__ sigma,
+                                                  const int* __restrict__ sys, Geometry g,
+                                                  int* __restrict__ key, int* __restrict__ bin_count,
+                                                  int* __restrict__ status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int a = idx[t];
+  float x = pos[3 * (int64_t)a + 0], y = pos[3 * (int64_t)a + 1], z = pos[3 * (int64_t)a + 2];
+  int bin;
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    atomicOr(status, kStatusNonFinite);
+    bin = g.periodic ? 0 : sys[t];
+  } else {
+    bin = g.periodic ? cell_of(x, y, z, g) : sys[t];
+  }
+  int k = sigma[t] * g.n_bins + bin;
+  key[t] = k;
+  atomicAdd(&bin_count[k], 1);
+}
+
+// Exclusive scan of the bin histogram by one workgroup; also seeds the
+// scatter cursors.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ count,
+                                                       int* __restrict__ start,
+                                                       int* __restrict__ cursor, int n) {
+  __shared__ int part[kScanThreads];
+  int tid = threadIdx.x;
+  int per = (n + kScanThreads - 1) / kScanThreads;
+  int lo = tid * per;
+  int hi = min(n, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += count[i];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the per-thread totals
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = tid == 0 ? 0 : part[tid - 1];
+  for (int i = lo; i < hi; ++i) {
+    start[i] = run;
+    cursor[i] = run;
+    run += count[i];
+  }
+  if (tid == kScanThreads - 1) start[n] = part[kScanThreads - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key, int n,
+                                                    int* __restrict__ cursor,
+                                                    int* __restrict__ tmp) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int slot = atomicAdd(&cursor[key[t]], 1);
+  tmp[slot] = t;
+}
+
+// One wavefront per bin: the atomically scattered entries of the bin are
+// ranked by atom index (a stable order independent of the atomic order), and
+// the sorted positions / species / atom indices are written per slot.
+__global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ start, int n_bins_total,
+                                                    const int* __restrict__ tmp,
+                                                    const float* __restrict__ pos,
+                                                    const int* __restrict__ idx,
+                                                    const int* __restrict__ sigma,
+                                                    int* __restrict__ perm,
+                                                    float4* __restrict__ spos,
+                                                    int* __restrict__ slot_atom) {
+  int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (wave >= n_bins_total) return;
+  int b0 = start[wave], b1 = start[wave + 1];
+  for (int p = b0 + lane; p < b1; p += 64) {
+    int t = tmp[p];
+    int rank = 0;
+    for (int q = b0; q < b1; ++q) rank += tmp[q] < t;
+    int slot = b0 + rank;
+    perm[slot] = t;
+    int a = idx[t];
+    float4 v;
+    v.x = pos[3 * (int64_t)a + 0];
+    v.y = pos[3 * (int64_t)a + 1];
+    v.z = pos[3 * (int64_t)a + 2];
+    v.w = __int_as_float(sigma[t]);
+    spos[slot] = v;
+    slot_atom[slot] = a;
+  }
+}
+
+struct NeighArgs {
+  const float4* spos;
+  const int* perm;
+  const int* key;
+  const int* bin_start;
+  int n, S;
+  float rc2, rca2;
+  int* rad;
+  int* ang;
+  int* rad_off;
+  int* ang_off;
+  int max_rad, max_ang;
+  int* status;
+};
+
+// One thread per sorted slot; candidates are scanned species by species so
+// each list comes out grouped by species.
+__global__ __launch_bounds__(kBlock) void k_neighbours(NeighArgs a, Geometry g) {
+#pragma clang fp contract(off)
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  float4 pi = a.spos[i];
+  int bin = a.key[a.perm[i]] % g.n_bins;
+  int c[3] = {0, 0, 0};
+  int nd[3] = {1, 1, 1};
+  int offs[3][3];
+  if (g.periodic) {
+    c[0] = bin / (g.nc[1] * g.nc[2]);
+    c[1] = (bin / g.nc[2]) % g.nc[1];
+    c[2] = bin % g.nc[2];
+    for (int k = 0; k < 3; ++k) {
+      if (g.nc[k] >= 3) {
+        nd[k] = 3; offs[k][0] = -1; offs[k][1] = 0; offs[k][2] = 1;
+      } else if (g.nc[k] == 2) {
+        nd[k] = 2; offs[k][0] = 0; offs[k][1] = 1;
+      } else {
+        nd[k] = 1; offs[k][0] = 0;
+      }
+    }
+  } else {
+    offs[0][0] = offs[1][0] = offs[2][0] = 0;
+  }
+  int* rad = a.rad + (int64_t)i * a.max_rad;
+  int* ang = a.ang + (int64_t)i * a.max_ang;
+  int nr = 0, na = 0;
+  for (int s = 0; s < a.S; ++s) {
+    a.rad_off[(int64_t)i * (a.S + 1) + s] = min(nr, a.max_rad);
+    a.ang_off[(int64_t)i * (a.S + 1) + s] = min(na, a.max_ang);
+    for (int ox = 0; ox < nd[0]; ++ox)
+      for (int oy = 0; oy < nd[1]; ++oy)
+        for (int oz = 0; oz < nd[2]; ++oz) {
+          int cb;
+          if (g.periodic) {
+            int x = c[0] + offs[0][ox]; x = x < 0 ? x + g.nc[0] : (x >= g.nc[0] ? x - g.nc[0] : x);
+            int y = c[1] + offs[1][oy]; y = y < 0 ? y + g.nc[1] : (y >= g.nc[1] ? y - g.nc[1] : y);
+            int z = c[2] + offs[2][oz]; z = z < 0 ? z + g.nc[2] : (z >= g.nc[2] ? z - g.nc[2] : z);
+            cb = (x * g.nc[1] + y) * g.nc[2] + z;
+          } else {
+            cb = bin;
+          }
+          int k = s * g.n_bins + cb;
+          int j0 = a.bin_start[k], j1 = a.bin_start[k + 1];
+          for (int j = j0; j < j1; ++j) {
+            if (j == i) continue;
+            float4 pj = a.spos[j];
+            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            if (g.periodic) {
+              float sx = rintf(dx * g.inv_box[0]);
+              float sy = rintf(dy * g.inv_box[1]);
+              float sz = rintf(dz * g.inv_box[2]);
+              float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+              dx = dx - tx; dy = dy - ty; dz = dz - tz;
+            }
+            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            float r2 = xx + yy;
+            r2 = r2 + zz;
+            if (r2 < a.rc2) {
+              if (nr < a.max_rad) rad[nr] = j;
+              ++nr;
+              if (r2 < a.rca2) {
+                if (na < a.max_ang) ang[na] = j;
+                ++na;
+              }
+            }
+          }
+        }
+  }
+  a.rad_off[(int64_t)i * (a.S + 1) + a.S] = min(nr, a.max_rad);
+  a.ang_off[(int64_t)i * (a.S + 1) + a.S] = min(na, a.max_ang);
+  if (nr > a.max_rad || na > a.max_ang) atomicOr(a.status, kStatusCapacity);
+}
+
+inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
+  const Geometry& g = m.geo;
+  int nb = m.S * g.n_bins;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nb, kBlock)), dim3(kBlock), 0, st,
+                       m.d_bin_count, nb, 0);
+  }
+  if (n > 0) {
+    hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
+                       m.d_sigma, m.d_sys, g, m.d_key, m.d_bin_count, m.d_status);
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start,
+                     m.d_cursor, nb);
+  if (n > 0) {
+    int* tmp = m.d_tmp;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
+                       m.d_cursor, tmp);
+    hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
+                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, m.d_perm, m.d_spos,
+                       m.d_slot_atom);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  NeighArgs a;
+  a.spos = m.d_spos;
+  a.perm = m.d_perm;
+  a.key = m.d_key;
+  a.bin_start = m.d_bin_start;
+  a.n = n;
+  a.S = m.S;
+  a.rc2 = m.dp.rc_rad * m.dp.rc_rad;
+  a.rca2 = m.dp.rc_ang * m.dp.rc_ang;
+  a.rad = m.d_nbr_rad;
+  a.ang = m.d_nbr_ang;
+  a.rad_off = m.d_rad_off;
+  a.ang_off = m.d_ang_off;
+  a.max_rad = m.max_rad;
+  a.max_ang = m.max_ang;
+  a.status = m.d_status;
+  hipLaunchKernelGGL(k_neighbours, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, a, m.geo);
+  return hipGetLastError();
+}
+
+}  // namespace nnp

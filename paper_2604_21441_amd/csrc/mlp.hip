@@ -1,0 +1,342 @@
+// Per-element networks on the matrix cores: forward (atomic energies) and the
+// hand-written backward (dE/d descriptor), fused in one kernel.
+//
+// Layout trick.  Each wavefront owns 16 atoms of one species and computes the
+// TRANSPOSED products  H_l^T [features x 16 atoms] = W_l [out x in] * H_{l-1}^T,
+// so the weights are the A operand and the activations the B operand of
+// v_mfma_f32_16x16x{4f32,32_bf16}.  The accumulator layout of one 16x16
+// output tile (lane = atom + 16 q holds features 4q..4q+3) is exactly the B
+// operand layout the next layer needs for a 16-wide (FP32) or, taking two
+// tiles, 32-wide (BF16) K block, provided the K dimension is permuted the same
+// way in the packed weights.  The whole chain -- three hidden layers, the
+// output layer, and the three backward products -- therefore stays in
+// registers: no LDS, no barriers.  Weights are pre-packed on the host in
+// fragment order (one 16-byte load per lane per MFMA step).
+//
+// Backward: e = w4 . h3 + b4, delta3 = w4 o celu'(u3), delta2 = (W3^T delta3) o
+// celu'(u2), delta1 = (W2^T delta2) o celu'(u1), dE/dx = W1^T delta1, with
+// celu'(u) recovered from h = celu(u): 1 for h > 0, else h/alpha + 1.
+// An ensemble averages e and dE/dx over its members.
+#include <type_traits>
+
+#include "nnp_internal.h"
+
+namespace nnp {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kBlock = 256;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ v4f mfma_step(const v4f& w, const v4f& b, v4f c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(w[0], b[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(w[1], b[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(w[2], b[2], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(w[3], b[3], c, 0, 0, 0);
+  return c;
+}
+
+__device__ __forceinline__ v8bf to_bf16x8(const v4f& lo, const v4f& hi) {
+  v8bf r;
+  r[0] = (__bf16)lo[0]; r[1] = (__bf16)lo[1]; r[2] = (__bf16)lo[2]; r[3] = (__bf16)lo[3];
+  r[4] = (__bf16)hi[0]; r[5] = (__bf16)hi[1]; r[6] = (__bf16)hi[2]; r[7] = (__bf16)hi[3];
+  return r;
+}
+
+// out[R/16 tiles] (+)= W[R x C] * in[C/16 tiles]; `in` is register resident.
+// Row tiles are processed in chunks of CH to bound the live accumulators.
+template <int R, int C, bool BF16, int CH>
+__device__ __forceinline__ void gemm_regs(const void* __restrict__ W, const v4f* in, v4f* out, int lane) {
+  static_assert(R % 16 == 0 && C % (BF16 ? 32 : 16) == 0, "tile sizes");
+  constexpr int RT = R / 16;
+#pragma unroll
+  for (int r0 = 0; r0 < RT; r0 += CH) {
+    if constexpr (!BF16) {
+      constexpr int KB = C / 16;
+      const v4f* Wp = reinterpret_cast<const v4f*>(W);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+        for (int r = r0; r < (r0 + CH < RT ? r0 + CH : RT); ++r) {
+          v4f w = Wp[(r * KB + kb) * 64 + lane];
+          out[r] = mfma_step(w, in[kb], out[r]);
+        }
+      }
+    } else {
+      constexpr int KB = C / 32;
+      const v8bf* Wp = reinterpret_cast<const v8bf*>(W);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        v8bf b = to_bf16x8(in[2 * kb], in[2 * kb + 1]);
+#pragma unroll
+        for (int r = r0; r < (r0 + CH < RT ? r0 + CH : RT); ++r) {
+          v8bf w = Wp[(r * KB + kb) * 64 + lane];
+          out[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, out[r], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float celu_f(float u, float alpha, float inv_alpha_l2) {
+  return u > 0.f ? u : alpha * (__builtin_amdgcn_exp2f(u * inv_alpha_l2) - 1.f);
+}
+__device__ __forceinline__ float celu_grad_from_h(float h, float inv_alpha) {
+  return h > 0.f ? 1.f : h * inv_alpha + 1.f;
+}
+
+// Packed per-(member, species) layout of the matrices, in elements:
+//   F1 [N1 x K0], F2 [N2 x N1], F3 [N3 x N2]   forward,  A = W_l
+//   B1 [K0 x N1], B2 [N1 x N2], B3 [N2 x N3]   backward, A = W_l^T
+// and of the vectors (FP32): b1[N1] b2[N2] b3[N3] w4[N3] b4[4].
+template <int K0, int N1, int N2, int N3, bool BF16>
+__global__ __launch_bounds__(kBlock) void k_mlp(MlpArgs a, float alpha) {
+  constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
+  constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
+  constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
+  using Elem = typename std::conditional<BF16, __bf16, float>::type;
+
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15;
+  const int q = lane >> 4;
+
+  // wave -> (species, 16-row tile) from the species bucket boundaries
+  int s = -1, row0 = 0, row_end = 0, before = 0;
+  for (int ss = 0; ss < a.S; ++ss) {
+    int b0 = a.bin_start[ss * a.n_bins], b1 = a.bin_start[(ss + 1) * a.n_bins];
+    int nt = (b1 - b0 + 15) >> 4;
+    if (wave < before + nt) {
+      s = ss;
+      row0 = b0 + (wave - before) * 16;
+      row_end = b1;
+      break;
+    }
+    before += nt;
+  }
+  if (s < 0) return;
+  const int row = row0 + col;
+  const bool valid = row < row_end;
+  const float inv_alpha = 1.f / alpha;
+  const float inv_alpha_l2 = kLog2e / alpha;
+  const float* xrow = a.x + (int64_t)row * a.stride;
+  float* grow = a.g + (int64_t)row * a.stride;
+  float e_sum = 0.f;
+
+  for (int mem = 0; mem < a.n_members; ++mem) {
+    const Elem* Wm = reinterpret_cast<const Elem*>(a.wmat) + (int64_t)(mem * a.S + s) * a.mat_per_species;
+    const float* V = a.wvec + (int64_t)(mem * a.S + s) * a.vec_per_species;
+
+    // ---- layer 1: h1 = celu(W1 x + b1); x streamed from memory
+    v4f h1[N1 / 16];
+#pragma unroll
+    for (int r = 0; r < N1 / 16; ++r) h1[r] = *reinterpret_cast<const v4f*>(V + ob1 + 16 * r + 4 * q);
+    if constexpr (!BF16) {
+      const v4f* Wp = reinterpret_cast<const v4f*>(Wm + oF1);
+#pragma unroll 2
+      for (int kb = 0; kb < K0 / 16; ++kb) {
+        v4f xb = valid ? *reinterpret_cast<const v4f*>(xrow + 16 * kb + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < N1 / 16; ++r) h1[r] = mfma_step(Wp[(r * (K0 / 16) + kb) * 64 + lane], xb, h1[r]);
+      }
+    } else {
+      const v8bf* Wp = reinterpret_cast<const v8bf*>(Wm + oF1);
+#pragma unroll 2
+      for (int kb = 0; kb < K0 / 32; ++kb) {
+        v4f lo = v4f{0.f, 0.f, 0.f, 0.f}, hi = v4f{0.f, 0.f, 0.f, 0.f};
+        if (valid) {
+          lo = *reinterpret_cast<const v4f*>(xrow + 32 * kb + 4 * q);
+          hi = *reinterpret_cast<const v4f*>(xrow + 32 * kb + 16 + 4 * q);
+        }
+        v8bf xb = to_bf16x8(lo, hi);
+#pragma unroll
+        for (int r = 0; r < N1 / 16; ++r)
+          h1[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wp[(r * (K0 / 32) + kb) * 64 + lane], xb, h1[r], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < N1 / 16; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) h1[r][t] = celu_f(h1[r][t], alpha, inv_alpha_l2);
+
+    // ---- layer 2
+    v4f h2[N2 / 16];
+#pragma unroll
+    for (int r = 0; r < N2 / 16; ++r) h2[r] = *reinterpret_cast<const v4f*>(V + ob2 + 16 * r + 4 * q);
+    gemm_regs<N2, N1, BF16, 4>(Wm + oF2, h1, h2, lane);
+#pragma unroll
+    for (int r = 0; r < N2 / 16; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) h2[r][t] = celu_f(h2[r][t], alpha, inv_alpha_l2);
+
+    // ---- layer 3
+    v4f h3[N3 / 16];
+#pragma unroll
+    for (int r = 0; r < N3 / 16; ++r) h3[r] = *reinterpret_cast<const v4f*>(V + ob3 + 16 * r + 4 * q);
+    gemm_regs<N3, N2, BF16, 4>(Wm + oF3, h2, h3, lane);
+#pragma unroll
+    for (int r = 0; r < N3 / 16; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) h3[r][t] = celu_f(h3[r][t], alpha, inv_alpha_l2);
+
+    // ---- output layer and delta3 (in place)
+    float ep = 0.f;
+#pragma unroll
+    for (int r = 0; r < N3 / 16; ++r) {
+      v4f w4 = *reinterpret_cast<const v4f*>(V + ow4 + 16 * r + 4 * q);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        ep += w4[t] * h3[r][t];
+        h3[r][t] = w4[t] * celu_grad_from_h(h3[r][t], inv_alpha);
+      }
+    }
+    ep += __shfl_xor(ep, 16, 64);
+    ep += __shfl_xor(ep, 32, 64);
+    e_sum += ep + V[ob4];
+
+    // ---- delta2 = (W3^T delta3) o celu'(h2)
+    v4f d2[N2 / 16];
+#pragma unroll
+    for (int r = 0; r < N2 / 16; ++r) d2[r] = v4f{0.f, 0.f, 0.f, 0.f};
+    gemm_regs<N2, N3, BF16, 4>(Wm + oB3, h3, d2, lane);
+#pragma unroll
+    for (int r = 0; r < N2 / 16; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) h2[r][t] = d2[r][t] * celu_grad_from_h(h2[r][t], inv_alpha);
+
+    // ---- delta1 = (W2^T delta2) o celu'(h1)
+    v4f d1[N1 / 16];
+#pragma unroll
+    for (int r = 0; r < N1 / 16; ++r) d1[r] = v4f{0.f, 0.f, 0.f, 0.f};
+    gemm_regs<N1, N2, BF16, 4>(Wm + oB2, h2, d1, lane);
+#pragma unroll
+    for (int r = 0; r < N1 / 16; ++r)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) h1[r][t] = d1[r][t] * celu_grad_from_h(h1[r][t], inv_alpha);
+
+    // ---- dE/dx = W1^T delta1, in chunks of row tiles streamed to memory
+    constexpr int CH = 8;
+    constexpr int RT0 = K0 / 16;
+#pragma unroll
+    for (int r0 = 0; r0 < RT0; r0 += CH) {
+      v4f gx[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) gx[c] = v4f{0.f, 0.f, 0.f, 0.f};
+      if constexpr (!BF16) {
+        const v4f* Wp = reinterpret_cast<const v4f*>(Wm + oB1);
+#pragma unroll
+        for (int kb = 0; kb < N1 / 16; ++kb)
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            if (r0 + c < RT0) gx[c] = mfma_step(Wp[((r0 + c) * (N1 / 16) + kb) * 64 + lane], h1[kb], gx[c]);
+      } else {
+        const v8bf* Wp = reinterpret_cast<const v8bf*>(Wm + oB1);
+#pragma unroll
+        for (int kb = 0; kb < N1 / 32; ++kb) {
+          v8bf b = to_bf16x8(h1[2 * kb], h1[2 * kb + 1]);
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            if (r0 + c < RT0)
+              gx[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wp[((r0 + c) * (N1 / 32) + kb) * 64 + lane], b, gx[c], 0, 0, 0);
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (r0 + c < RT0) {
+            v4f* dst = reinterpret_cast<v4f*>(grow + 16 * (r0 + c) + 4 * q);
+            v4f v = gx[c];
+            if (a.n_members > 1) {
+              if (mem > 0) v += *dst;
+              if (mem == a.n_members - 1) v *= (1.f / (float)a.n_members);
+            }
+            *dst = v;
+          }
+        }
+      }
+    }
+  }
+  if (valid && q == 0) a.e[row] = e_sum / (float)a.n_members;
+}
+
+// Per-system FP64 energy: a fixed-order block reduction (deterministic).
+constexpr int kRed = 256;
+__global__ __launch_bounds__(kRed) void k_energy(const float* __restrict__ e, const int* __restrict__ bin_start,
+                                                 int n_bins, int S, int single, double* __restrict__ out,
+                                                 int accumulate, int* __restrict__ status) {
+  __shared__ double part[kRed];
+  const int sys = blockIdx.x;
+  double acc = 0.0;
+  if (single) {
+    int n = bin_start[S * n_bins];
+    for (int t = threadIdx.x; t < n; t += kRed) acc += (double)e[t];
+  } else {
+    for (int s = 0; s < S; ++s) {
+      int b0 = bin_start[s * n_bins + sys], b1 = bin_start[s * n_bins + sys + 1];
+      for (int t = b0 + threadIdx.x; t < b1; t += kRed) acc += (double)e[t];
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kRed / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double v = part[0];
+    if (!isfinite(v)) atomicOr(status, kStatusNonFinite);
+    out[sys] = accumulate ? out[sys] + v : v;
+  }
+}
+
+template <int K0, int N1, int N2, int N3, bool BF16>
+hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, hipStream_t st) {
+  int64_t tiles = (n + 15) / 16 + m.S;
+  int64_t threads = tiles * 64;
+  hipLaunchKernelGGL((k_mlp<K0, N1, N2, N3, BF16>), dim3((unsigned)((threads + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, st, a, m.celu_alpha);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  MlpArgs a;
+  a.x = m.d_x;
+  a.g = m.d_g;
+  a.e = m.d_e;
+  a.wmat = m.d_wmat;
+  a.wvec = m.d_wvec;
+  a.bin_start = m.d_bin_start;
+  a.n_bins = m.geo.n_bins;
+  a.S = m.S;
+  a.n_members = m.n_members;
+  a.stride = m.stride;
+  a.mat_per_species = m.mat_per_species;
+  a.vec_per_species = m.vec_per_species;
+  a.status = m.d_status;
+  const bool bf = m.prec == NNP_BF16;
+  switch (m.net_kind) {
+    case 0:
+      return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, st);
+    case 1:
+      return bf ? run_mlp<384, 256, 192, 160, true>(m, a, n, st) : run_mlp<384, 256, 192, 160, false>(m, a, n, st);
+    case 2:
+      return bf ? run_mlp<416, 256, 192, 160, true>(m, a, n, st) : run_mlp<416, 256, 192, 160, false>(m, a, n, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st) {
+  int single = m.geo.periodic || n_sys == 1 ? 1 : 0;
+  int blocks = single ? 1 : n_sys;
+  hipLaunchKernelGGL(k_energy, dim3(blocks), dim3(kRed), 0, st, m.d_e, m.d_bin_start, m.geo.n_bins, m.S, single,
+                     energies, accumulate, m.d_status);
+  return hipGetLastError();
+}
+
+}  // namespace nnp

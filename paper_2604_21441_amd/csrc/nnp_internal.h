@@ -1,0 +1,162 @@
+// Internal declarations of the NNP library: model state, kernel parameter
+// blocks and the launchers of each stage.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nnp.h"
+
+namespace nnp {
+
+constexpr int kRadShifts = 16;   // radial shifts per species
+constexpr int kAngShifts = 8;    // angular radial shifts per species pair
+constexpr int kAngSects = 4;     // angle sections per species pair
+constexpr int kMaxSpecies = 4;
+constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
+constexpr int kTileAtoms = 16;   // atoms per wavefront in the network kernels
+
+// Device status bits.
+constexpr int kStatusCapacity = 1;
+constexpr int kStatusNonFinite = 2;
+
+// Descriptor constants, passed by value to the kernels.
+struct DescParams {
+  float rc_rad, rc_ang;
+  float eta_rad, eta_ang, zeta;
+  float ang_pref;                       // 2^(1 - zeta)
+  float rad_shift[kRadShifts];
+  float ang_shift[kAngShifts];
+  float cos_sect[kAngSects], sin_sect[kAngSects];
+  float mm_cutoff, ke;
+  int S, P, D, stride;                  // species, pair classes, descriptor length, row stride
+  int extra;                            // 1 if the MM potential is the last input
+  int pair_a[kMaxPairs], pair_b[kMaxPairs];
+};
+
+// Geometry of the current call.
+struct Geometry {
+  int periodic;                         // 1: orthorhombic minimum image
+  float box[3], inv_box[3];
+  int nc[3];                            // cells per dimension (periodic)
+  float cell_scale[3];                  // nc * (1/L) in FP32
+  int n_bins;                           // cells (periodic) or systems (batched)
+};
+
+// Neighbour-list arrays (per sorted slot).
+struct NbrLists {
+  int* rad;      // [n][max_rad]
+  int* ang;      // [n][max_ang]
+  int* rad_off;  // [n][S+1] segment starts by species within the row
+  int* ang_off;  // [n][S+1]
+  int max_rad, max_ang;
+};
+
+// Network tile schedule: species buckets are bins [s*n_bins, (s+1)*n_bins).
+struct MlpArgs {
+  const float* x;          // [n][stride]
+  float* g;                // [n][stride]  dE/dx (output)
+  float* e;                // [n] atomic energies (output)
+  const void* wmat;        // fragment-packed matrices (FP32 or BF16)
+  const float* wvec;       // biases and output weights (FP32)
+  const int* bin_start;    // species bucket boundaries
+  int n_bins, S, n_members, stride;
+  int64_t mat_per_species; // elements per (member, species) in wmat
+  int64_t vec_per_species; // elements per (member, species) in wvec
+  int* status;
+};
+
+}  // namespace nnp
+
+// The model object.
+struct nnp_model {
+  int device = 0;
+  nnp_precision prec = NNP_FP32;
+  int S = 0, P = 0, D = 0, Din = 0, stride = 0, n_members = 1, extra = 0;
+  std::vector<int> species;             // atomic numbers, ascending
+  std::vector<int> widths;              // unpadded widths
+  float celu_alpha = 0.1f;
+  nnp::DescParams dp{};
+  int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
+  std::vector<float> w_host;            // canonical FP32 weights, draw order
+
+  // device weights
+  void* d_wmat = nullptr;
+  float* d_wvec = nullptr;
+  int64_t mat_per_species = 0, vec_per_species = 0;
+
+  // capacities
+  int max_atoms = 0, max_sys = 0, max_mm = 0, max_rad = 0, max_ang = 0, max_bins = 0;
+  bool reserved = false;
+
+  // workspace (device)
+  int* d_idx = nullptr;        // NNP-local atom -> atom index
+  int* d_sigma = nullptr;      // NNP-local atom -> species
+  int* d_sys = nullptr;        // NNP-local atom -> system (batched)
+  int* d_key = nullptr;
+  int* d_bin_count = nullptr;
+  int* d_bin_start = nullptr;  // [max_bins + 1]
+  int* d_cursor = nullptr;
+  int* d_perm = nullptr;       // slot -> NNP-local atom
+  int* d_tmp = nullptr;        // scatter order before the in-bin ranking
+  float4* d_spos = nullptr;    // slot -> position (w = species bits)
+  int* d_slot_atom = nullptr;  // slot -> atom index
+  int* d_nbr_rad = nullptr;
+  int* d_nbr_ang = nullptr;
+  int* d_rad_off = nullptr;
+  int* d_ang_off = nullptr;
+  float* d_x = nullptr;
+  float* d_g = nullptr;
+  float* d_e = nullptr;
+  double* d_phi = nullptr;     // MM potential accumulator [max_atoms]
+  int* d_status = nullptr;
+  int* h_stage = nullptr;      // pinned staging for topology uploads
+
+  // topology cache (host copies)
+  int topo_mode = -1;          // 0 single system, 1 batched
+  int topo_n_atoms = -1;
+  std::vector<int> topo_Z, topo_idx, topo_offsets;
+  int n_nnp = 0;
+
+  // last call
+  nnp::Geometry geo{};
+  int last_n = 0;
+};
+
+namespace nnp {
+
+// error helpers (api.cpp)
+nnp_status set_error(nnp_status s, const std::string& msg);
+nnp_status hip_error(hipError_t e, const char* what);
+
+// weights.cpp
+void draw_weights(uint64_t seed, const std::vector<int>& widths, int n_species, int n_members,
+                  std::vector<float>& out);
+void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<float>& vec,
+                  int64_t& mat_per_species, int64_t& vec_per_species);
+
+// cells.hip
+hipError_t launch_cells(nnp_model& m, const float* pos, int n_nnp, hipStream_t st);
+hipError_t launch_neighbours(nnp_model& m, int n_nnp, hipStream_t st);
+
+// descriptor.hip
+hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st);
+hipError_t launch_descriptor_bwd(nnp_model& m, int n, double* forces, hipStream_t st);
+
+// mm.hip
+hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
+                         hipStream_t st);
+hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
+                         double* forces, double* mm_forces, hipStream_t st);
+
+// mlp.hip
+hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st);
+hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st);
+
+// fills (api.cpp)
+hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t st);
+
+}  // namespace nnp

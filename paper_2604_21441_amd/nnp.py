@@ -1,0 +1,253 @@
+"""Python binding of the NNP library: the C ABI's calls under the same names,
+a small ``NNPModel`` convenience class, and ``NNPEnergy``, a
+torch.autograd.Function whose backward returns -dE/dx from the library's
+hand-written adjoint.
+
+Everything here is argument marshalling: device pointers come from torch
+CUDA tensors and the stream is torch's current stream; every stage of the
+computation runs in the HIP kernels of libnnp.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
+    "nnp_read_buffer", "nnp_destroy", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "make_config", "NNPModel", "NNPEnergy",
+]
+
+
+class NNPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        self.status = status
+        msg = lib.nnp_last_error().decode() or lib.nnp_status_string(status).decode()
+        super().__init__(f"{where}: {lib.nnp_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != L.NNP_OK:
+        raise NNPError(status, where)
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dptr(t: torch.Tensor | None, dtype: torch.dtype, what: str):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype, what):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    ctype = C.c_int32 if dtype == np.int32 else C.c_float
+    return arr, arr.ctypes.data_as(C.POINTER(ctype))
+
+
+# ----------------------------------------------------------------- raw calls
+def nnp_version() -> str:
+    return L.load().nnp_version().decode()
+
+
+def nnp_status_string(s: int) -> str:
+    return L.load().nnp_status_string(s).decode()
+
+
+def nnp_last_error() -> str:
+    return L.load().nnp_last_error().decode()
+
+
+def make_config(cfg: dict, n_members: int = 1):
+    """Build the C nnp_config from a hyper-parameter dict.  Returns (struct, keepalive)."""
+    keep = []
+
+    def arr(a, dt):
+        x = np.ascontiguousarray(np.asarray(a), dtype=dt)
+        keep.append(x)
+        return x.ctypes.data_as(C.POINTER(C.c_int32 if dt == np.int32 else C.c_float))
+
+    c = L.nnp_config()
+    c.n_species = len(cfg["species"])
+    c.atomic_numbers_host = arr(cfg["species"], np.int32)
+    c.rc_rad, c.rc_ang = float(cfg["rc_rad"]), float(cfg["rc_ang"])
+    c.eta_rad, c.eta_ang, c.zeta = float(cfg["eta_rad"]), float(cfg["eta_ang"]), float(cfg["zeta"])
+    c.n_rad_shift = len(cfg["rad_shift"])
+    c.n_ang_shift = len(cfg["ang_shift"])
+    c.n_ang_sect = len(cfg["ang_sect"])
+    c.rad_shift_host = arr(cfg["rad_shift"], np.float32)
+    c.ang_shift_host = arr(cfg["ang_shift"], np.float32)
+    c.ang_sect_host = arr(cfg["ang_sect"], np.float32)
+    c.n_layers = len(cfg["widths"])
+    c.widths_host = arr(cfg["widths"], np.int32)
+    c.celu_alpha = float(cfg["celu_alpha"])
+    c.extra_inputs = int(cfg.get("extra_inputs", 0))
+    c.mm_cutoff = float(cfg.get("mm_cutoff", 12.0))
+    c.ke_coulomb = float(cfg.get("ke_coulomb", 14.3996454784))
+    c.n_members = int(n_members)
+    return c, keep
+
+
+def nnp_create(cfg: dict, seed: int = 1, weights=None, precision: str = "fp32", n_members: int = 1) -> C.c_void_p:
+    lib = L.load()
+    c, keep = make_config(cfg, n_members)
+    w, wp = _host(weights, np.float32, "weights") if weights is not None else (None, None)
+    h = C.c_void_p()
+    prec = {"fp32": L.NNP_FP32, "bf16": L.NNP_BF16}[precision]
+    _check(lib.nnp_create(C.byref(c), C.c_uint64(seed), wp, prec, C.byref(h)), "nnp_create")
+    del keep, w
+    return h
+
+
+def nnp_reserve(h, max_atoms: int, max_systems: int = 1, max_mm: int = 0, max_rad_nbr: int = 0,
+                max_ang_nbr: int = 0) -> None:
+    _check(L.load().nnp_reserve(h, max_atoms, max_systems, max_mm, max_rad_nbr, max_ang_nbr), "nnp_reserve")
+
+
+def nnp_compute(h, pos: torch.Tensor, Z, box, nnp_idx, mm_pos, mm_q, energy: torch.Tensor, forces: torch.Tensor,
+                mm_forces=None, accumulate: bool = False, stream=None) -> None:
+    n = pos.shape[0]
+    Za, Zp = _host(Z, np.int32, "Z")
+    Ia, Ip = _host(nnp_idx, np.int32, "nnp_idx")
+    Ba, Bp = _host(box, np.float32, "box")
+    n_nnp = n if Ia is None else Ia.size
+    n_mm = 0 if mm_pos is None else mm_pos.shape[0]
+    st = L.load().nnp_compute(h, n, _dptr(pos, torch.float32, "pos"), Zp, Bp, n_nnp, Ip, n_mm,
+                              _dptr(mm_pos, torch.float32, "mm_pos"), _dptr(mm_q, torch.float32, "mm_q"),
+                              _dptr(energy, torch.float64, "energy"), _dptr(forces, torch.float64, "forces"),
+                              _dptr(mm_forces, torch.float64, "mm_forces"), 1 if accumulate else 0,
+                              _stream(stream))
+    _check(st, "nnp_compute")
+
+
+def nnp_compute_batch(h, offsets, pos: torch.Tensor, Z, energies: torch.Tensor, forces: torch.Tensor,
+                      stream=None) -> None:
+    Oa, Op = _host(offsets, np.int32, "offsets")
+    Za, Zp = _host(Z, np.int32, "Z")
+    st = L.load().nnp_compute_batch(h, Oa.size - 1, Op, _dptr(pos, torch.float32, "pos"), Zp,
+                                    _dptr(energies, torch.float64, "energies"),
+                                    _dptr(forces, torch.float64, "forces"), _stream(stream))
+    _check(st, "nnp_compute_batch")
+
+
+def nnp_get_status(h, stream=None) -> int:
+    return L.load().nnp_get_status(h, _stream(stream))
+
+
+def nnp_read_buffer(h, which: int, stream=None) -> np.ndarray:
+    lib = L.load()
+    elems = C.c_int64()
+    stride = C.c_int32()
+    _check(lib.nnp_read_buffer(h, which, None, 0, C.byref(elems), C.byref(stride), _stream(stream)),
+           "nnp_read_buffer")
+    dt = np.float32 if which in (L.NNP_BUF_DESCRIPTOR, L.NNP_BUF_ATOM_ENERGY, L.NNP_BUF_DEDX) else np.int32
+    out = np.empty(elems.value, dtype=dt)
+    _check(lib.nnp_read_buffer(h, which, out.ctypes.data_as(C.c_void_p), out.nbytes, C.byref(elems),
+                               C.byref(stride), _stream(stream)), "nnp_read_buffer")
+    if stride.value > 1:
+        out = out.reshape(-1, stride.value)
+    return out
+
+
+def nnp_destroy(h) -> None:
+    L.load().nnp_destroy(h)
+
+
+# ------------------------------------------------------------ convenience
+class NNPModel:
+    """Owns one library model on the current device."""
+
+    def __init__(self, cfg: dict, seed: int = 1, weights=None, precision: str = "fp32", n_members: int = 1):
+        self.cfg = cfg
+        self.precision = precision
+        self.h = nnp_create(cfg, seed, weights, precision, n_members)
+        self.capacity = None
+
+    def reserve(self, max_atoms: int, max_systems: int = 1, max_mm: int = 0, max_rad_nbr: int = 0,
+                max_ang_nbr: int = 0) -> None:
+        nnp_reserve(self.h, max_atoms, max_systems, max_mm, max_rad_nbr, max_ang_nbr)
+        self.capacity = (max_atoms, max_systems, max_mm, max_rad_nbr, max_ang_nbr)
+
+    def _ensure(self, n_atoms: int, n_sys: int = 1, n_mm: int = 0) -> None:
+        c = self.capacity
+        if c is None or n_atoms > c[0] or n_sys > c[1] or n_mm > c[2]:
+            base = c if c is not None else (0, 1, 0, 0, 0)
+            self.reserve(max(n_atoms, base[0]), max(n_sys, base[1]), max(n_mm, base[2]), base[3], base[4])
+
+    def compute(self, pos: torch.Tensor, Z=None, box=None, nnp_idx=None, mm_pos=None, mm_q=None,
+                accumulate_into=None, stream=None):
+        """Energy [1] (float64) and forces [n, 3] (float64) on pos.device; MM forces if MM charges are given."""
+        n = pos.shape[0]
+        self._ensure(n, 1, 0 if mm_pos is None else mm_pos.shape[0])
+        dev = pos.device
+        if accumulate_into is not None:
+            E, F, Fmm = accumulate_into
+        else:
+            E = torch.empty(1, dtype=torch.float64, device=dev)
+            F = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            Fmm = None if mm_pos is None else torch.empty((mm_pos.shape[0], 3), dtype=torch.float64, device=dev)
+        nnp_compute(self.h, pos, Z, box, nnp_idx, mm_pos, mm_q, E, F, Fmm,
+                    accumulate=accumulate_into is not None, stream=stream)
+        return E, F, Fmm
+
+    def compute_batch(self, pos: torch.Tensor, Z, offsets, stream=None):
+        offsets = np.asarray(offsets, dtype=np.int32)
+        self._ensure(pos.shape[0], offsets.size - 1)
+        E = torch.empty(offsets.size - 1, dtype=torch.float64, device=pos.device)
+        F = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
+        nnp_compute_batch(self.h, offsets, pos, Z, E, F, stream=stream)
+        return E, F
+
+    def status(self, stream=None) -> int:
+        return nnp_get_status(self.h, stream)
+
+    def read(self, which: int) -> np.ndarray:
+        return nnp_read_buffer(self.h, which)
+
+    def energy(self, pos: torch.Tensor, Z=None, box=None, nnp_idx=None):
+        """Differentiable E_ML(pos): backward gives -forces via the library's adjoint."""
+        return NNPEnergy.apply(pos, self, Z, box, nnp_idx)
+
+    def close(self) -> None:
+        if self.h:
+            nnp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class NNPEnergy(torch.autograd.Function):
+    """E = NNPEnergy.apply(pos, model, Z, box, nnp_idx); dE/dpos = -F from the same call."""
+
+    @staticmethod
+    def forward(ctx, pos, model, Z, box, nnp_idx):
+        p = pos.detach()
+        if p.dtype != torch.float32:
+            p = p.float()
+        E, F, _ = model.compute(p.contiguous(), Z, box, nnp_idx)
+        ctx.save_for_backward(F)
+        ctx.in_dtype = pos.dtype
+        return E[0].to(pos.dtype) if pos.dtype == torch.float64 else E[0]
+
+    @staticmethod
+    def backward(ctx, gE):
+        (F,) = ctx.saved_tensors
+        grad = -(gE.to(torch.float64) * F)
+        return grad.to(ctx.in_dtype), None, None, None, None

@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Integer stages (cell binning, the stable counting sort, neighbour sets) are
+compared bit for bit with the oracle's FP32 definitions; floating-point stages
+within the stated tolerances:
+  FP32 form: force relative RMSE <= 1e-5, energy error per atom <= 1e-6 eV;
+  BF16 form: force relative RMSE <= 1e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synthetic as sy
+
+pytestmark = pytest.mark.gpu
+
+WATER = sy.model_config("water")
+HCNO = sy.model_config("hcno")
+HCNO_MM = sy.model_config("hcno_mm")
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    import paper_2604_21441_amd as P
+    return P
+
+
+def rel_rmse(F, Fref):
+    return float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
+
+
+@pytest.fixture(scope="module")
+def P():
+    return _lib()
+
+
+@pytest.fixture(scope="module")
+def w_water():
+    return sy.model_weights(WATER, seed=1)
+
+
+@pytest.fixture(scope="module")
+def w_hcno():
+    return sy.model_weights(HCNO, seed=1)
+
+
+@pytest.fixture(scope="module")
+def water_models(P, w_water):
+    flat = sy.flat_weights(w_water)
+    return {p: P.NNPModel(WATER, weights=flat, precision=p) for p in ("fp32", "bf16")}
+
+
+@pytest.fixture(scope="module")
+def boxes():
+    return {"c1": sy.water_box(64, 12.42, seed=0), "c2": sy.water_box(4096, 49.7, seed=0)}
+
+
+@pytest.fixture(scope="module")
+def oracle_res(boxes, w_water):
+    out = {}
+    for k, (pos, Z, box) in boxes.items():
+        out[k] = orc.evaluate(pos, Z, WATER, w_water, box=box, return_x=True)
+    return out
+
+
+def _run(model, pos, Z, box, **kw):
+    d = torch.from_numpy(pos).cuda()
+    E, F, Fmm = model.compute(d, Z, box, **kw)
+    torch.cuda.synchronize()
+    assert model.status() == 0
+    return E.cpu().numpy(), F.cpu().numpy(), (None if Fmm is None else Fmm.cpu().numpy())
+
+
+# ------------------------------------------------------------ integer stages
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_cell_list_bit_exact(P, water_models, boxes, name):
+    pos, Z, box = boxes[name]
+    m = water_models["fp32"]
+    _run(m, pos, Z, box)
+    sigma = orc.species_index(Z, WATER["species"])
+    ref = orc.cell_list_fp32(pos, sigma, 2, box, WATER["rc_rad"])
+    grid = m.read(P._lib.NNP_BUF_GRID)
+    assert list(grid[1:]) == list(ref["n_c"])
+    assert np.array_equal(m.read(P._lib.NNP_BUF_KEY), ref["key"])
+    assert np.array_equal(m.read(P._lib.NNP_BUF_PERM), ref["perm"])
+    assert np.array_equal(m.read(P._lib.NNP_BUF_BIN_START), ref["bin_start"])
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_neighbour_sets_bit_exact(P, water_models, boxes, name):
+    pos, Z, box = boxes[name]
+    m = water_models["fp32"]
+    _run(m, pos, Z, box)
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    cnt = m.read(P._lib.NNP_BUF_NBR_COUNT)
+    sigma = orc.species_index(Z, WATER["species"])
+    for buf, rc, col in ((P._lib.NNP_BUF_NBR_RAD, WATER["rc_rad"], 0), (P._lib.NNP_BUF_NBR_ANG, WATER["rc_ang"], 1)):
+        lists = m.read(buf)
+        I, J = orc.neighbours_fp32(pos, rc, box)
+        ref = set(zip(I.tolist(), J.tolist()))
+        got = set()
+        for i in range(len(perm)):
+            row = lists[i, :cnt[i, col]]
+            sp = sigma[perm[row]]
+            assert np.all(np.diff(sp) >= 0), "neighbour row not grouped by species"
+            got.update((int(perm[i]), int(perm[j])) for j in row)
+        assert got == ref
+
+
+# ------------------------------------------------------- floating-point stages
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_descriptors_fp32(P, water_models, boxes, oracle_res, name):
+    pos, Z, box = boxes[name]
+    m = water_models["fp32"]
+    _run(m, pos, Z, box)
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    x = m.read(P._lib.NNP_BUF_DESCRIPTOR)[:, :128]
+    xr = np.empty_like(x, dtype=np.float64)
+    xr[perm] = x
+    ref = oracle_res[name]["x"]
+    err = np.linalg.norm(xr - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() < 1e-5, err.max()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_network_stage_fp32(P, water_models, boxes, oracle_res, w_water, name):
+    pos, Z, box = boxes[name]
+    m = water_models["fp32"]
+    _run(m, pos, Z, box)
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    e = np.empty(len(perm))
+    e[perm] = m.read(P._lib.NNP_BUF_ATOM_ENERGY)
+    g = m.read(P._lib.NNP_BUF_DEDX)[:, :128]
+    gr = np.empty(g.shape)
+    gr[perm] = g
+    sigma = orc.species_index(Z, WATER["species"])
+    e_ref, g_ref = orc.mlp_input_grad(oracle_res[name]["x"], sigma, w_water[0], WATER["celu_alpha"])
+    assert np.abs(e - e_ref).max() < 2e-5 * max(1.0, np.abs(e_ref).max())
+    assert rel_rmse(gr, g_ref) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_energy_forces_fp32(P, water_models, boxes, oracle_res, name):
+    pos, Z, box = boxes[name]
+    E, F, _ = _run(water_models["fp32"], pos, Z, box)
+    ref = oracle_res[name]
+    n = len(Z)
+    assert abs(E[0] - ref["E"]) / n < 1e-6
+    assert rel_rmse(F, ref["F"]) < 1e-5
+    assert np.abs(F.sum(0)).max() < 1e-6 * np.abs(F).max() * math.sqrt(n)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_energy_forces_bf16(P, water_models, boxes, oracle_res, name):
+    pos, Z, box = boxes[name]
+    E, F, _ = _run(water_models["bf16"], pos, Z, box)
+    ref = oracle_res[name]
+    n = len(Z)
+    assert abs(E[0] - ref["E"]) / n < 1e-2
+    assert rel_rmse(F, ref["F"]) < 1e-2
+
+
+def test_forces_match_gpu_finite_differences(P, water_models, boxes):
+    """The adjoint agrees with central differences of the GPU's own FP32 energy."""
+    pos, Z, box = boxes["c2"]
+    m = water_models["fp32"]
+    E0, F, _ = _run(m, pos, Z, box)
+    rng = np.random.default_rng(3)
+    h = 3e-3
+    for a in rng.choice(len(Z), 8, replace=False):
+        for k in range(3):
+            p1 = pos.copy(); p1[a, k] += h
+            p2 = pos.copy(); p2[a, k] -= h
+            dh = float(p1[a, k]) - float(p2[a, k])
+            e1 = _run(m, p1, Z, box)[0][0]
+            e2 = _run(m, p2, Z, box)[0][0]
+            fd = -(e1 - e2) / dh
+            assert abs(fd - F[a, k]) < 3e-3 * max(1.0, abs(F[a, k])), (a, k, fd, F[a, k])
+
+
+def test_index_group_subset(P, water_models, boxes, w_water):
+    pos, Z, box = boxes["c1"]
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(len(Z), 100, replace=False)).astype(np.int32)
+    E, F, _ = _run(water_models["fp32"], pos, Z, box, nnp_idx=idx)
+    ref = orc.evaluate(pos, Z, WATER, w_water, box=box, nnp_idx=idx)
+    assert abs(E[0] - ref["E"]) / idx.size < 1e-6
+    mask = np.ones(len(Z), bool)
+    mask[idx] = False
+    assert np.all(F[mask] == 0.0)
+    assert rel_rmse(F[idx], ref["F"][idx]) < 1e-5
+
+
+def test_accumulate_and_determinism(P, water_models, boxes):
+    pos, Z, box = boxes["c2"]
+    m = water_models["fp32"]
+    d = torch.from_numpy(pos).cuda()
+    E1, F1, _ = m.compute(d, Z, box)
+    E2, F2, _ = m.compute(d, Z, box)
+    torch.cuda.synchronize()
+    assert E1.item() == E2.item()                       # fixed-order FP64 energy sum
+    assert torch.allclose(F1, F2, rtol=0, atol=1e-10)   # FP64 atomics: order only
+    m.compute(d, Z, box, accumulate_into=(E1, F1, None))
+    torch.cuda.synchronize()
+    assert abs(E1.item() - 2 * E2.item()) < 1e-9 * abs(E2.item())
+    assert torch.allclose(F1, 2 * F2, rtol=1e-12, atol=1e-10)
+
+
+def test_autograd_function(P, water_models, boxes):
+    pos, Z, box = boxes["c1"]
+    m = water_models["fp32"]
+    x = torch.from_numpy(pos).cuda().requires_grad_(True)
+    E = m.energy(x, Z, box)
+    E.backward()
+    _, F, _ = m.compute(x.detach(), Z, box)
+    assert torch.allclose(x.grad.double(), -F.double(), rtol=1e-5, atol=1e-6)
+
+
+# ------------------------------------------------------------------ batching
+def test_batched_open_systems(P, w_hcno):
+    pos, Z, off = sy.walk_batch(12, seed=4)
+    flat = sy.flat_weights(w_hcno)
+    for prec, tol in (("fp32", 1e-5), ("bf16", 1e-2)):
+        m = P.NNPModel(HCNO, weights=flat, precision=prec)
+        E, F = m.compute_batch(torch.from_numpy(pos).cuda(), Z, off)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        E = E.cpu().numpy()
+        F = F.cpu().numpy()
+        Eref, Fref = orc.evaluate_batch(pos, Z, off, HCNO, w_hcno)
+        n = np.diff(off)
+        assert np.all(np.abs(E - Eref) / n < (1e-6 if prec == "fp32" else 1e-2))
+        assert rel_rmse(F, Fref) < tol
+        if prec == "fp32":
+            # one batched call equals separate open-system calls
+            for s in (0, 5, 11):
+                a, b = off[s], off[s + 1]
+                Es, Fs, _ = m.compute(torch.from_numpy(pos[a:b].copy()).cuda(), Z[a:b], None)
+                torch.cuda.synchronize()
+                assert abs(Es.item() - E[s]) < 1e-12 * max(1.0, abs(E[s]))
+                assert np.allclose(Fs.cpu().numpy(), F[a:b], rtol=0, atol=1e-9)
+        m.close()
+
+
+# ---------------------------------------------------------------- MM charges
+def test_mm_charge_channel(P):
+    sysd = sy.solute_in_water(seed=0)
+    w = sy.model_weights(HCNO_MM, seed=3)
+    ref = orc.evaluate(sysd["pos"], sysd["Z"], HCNO_MM, w, box=sysd["box"], mm_pos=sysd["mm_pos"],
+                       mm_q=sysd["mm_q"])
+    m = P.NNPModel(HCNO_MM, weights=sy.flat_weights(w), precision="fp32")
+    E, F, Fmm = _run(m, sysd["pos"], sysd["Z"], sysd["box"], mm_pos=torch.from_numpy(sysd["mm_pos"]).cuda(),
+                     mm_q=torch.from_numpy(sysd["mm_q"]).cuda())
+    n = len(sysd["Z"])
+    assert abs(E[0] - ref["E"]) / n < 1e-6
+    assert rel_rmse(F, ref["F"]) < 1e-5
+    Fall = np.concatenate([F, Fmm])
+    Fall_ref = np.concatenate([ref["F"], ref["F_mm"]])
+    assert rel_rmse(Fall, Fall_ref) < 1e-5
+    assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
+
+
+# ------------------------------------------------------------- error paths
+def test_error_paths(P, w_water):
+    m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+    pos, Z, box = sy.water_box(64, 12.42, seed=0)
+    d = torch.from_numpy(pos).cuda()
+    m.reserve(len(Z))
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    F = torch.empty((len(Z), 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.NNPError) as ex:
+        Zb = Z.copy(); Zb[5] = 6
+        P.nnp_compute(m.h, d, Zb, box, None, None, None, E, F)
+    assert ex.value.status == P._lib.NNP_ESPECIES
+    with pytest.raises(P.NNPError) as ex:
+        P.nnp_compute(m.h, d, Z, np.array([10.0, 12.42, 12.42], np.float32), None, None, None, E, F)
+    assert ex.value.status == P._lib.NNP_EBOX
+    big = torch.zeros((len(Z) + 1, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.NNPError) as ex:
+        P.nnp_compute(m.h, big, np.ones(len(Z) + 1, np.int32), box, None, None, None, E, F)
+    assert ex.value.status == P._lib.NNP_ECAPACITY
+    # neighbour capacity overflow is reported by the device status word
+    m.reserve(len(Z), 1, 0, 4, 2)
+    P.nnp_compute(m.h, d, Z, box, None, None, None, E, F)
+    assert m.status() == P._lib.NNP_ECAPACITY
+    assert m.status() == P._lib.NNP_OK     # cleared by the read
+    m.reserve(len(Z))
+    bad = pos.copy(); bad[3, 1] = np.nan
+    P.nnp_compute(m.h, torch.from_numpy(bad).cuda(), Z, box, None, None, None, E, F)
+    assert m.status() == P._lib.NNP_ENONFINITE
+    m.close()
+
+
+# ------------------------------------------- full-size sampled parity (98k)
+def test_c3_sampled_parity_fp32_bf16(P, water_models, w_water):
+    pos, Z, box = sy.water_box(32768, 99.4, seed=0)
+    res = {}
+    for prec in ("fp32", "bf16"):
+        E, F, _ = _run(water_models[prec], pos, Z, box)
+        perm = water_models[prec].read(P._lib.NNP_BUF_PERM)
+        e = np.empty(len(perm))
+        e[perm] = water_models[prec].read(P._lib.NNP_BUF_ATOM_ENERGY)
+        res[prec] = (E, F, e)
+    rng = np.random.default_rng(9)
+    sample = np.sort(rng.choice(len(Z), 24, replace=False))
+    I, J = orc.neighbour_pairs(pos, float(WATER["rc_rad"]), box, centres=sample)
+    cs = np.unique(np.concatenate([sample, J]))
+    ref = orc.evaluate(pos, Z, WATER, w_water, box=box, centres=cs)
+    e_ref = dict(zip(cs.tolist(), ref["e"]))
+    F32 = res["fp32"][1][sample]
+    assert rel_rmse(F32, ref["F"][sample]) < 1e-5
+    assert max(abs(res["fp32"][2][a] - e_ref[a]) for a in sample) < 2e-5
+    assert rel_rmse(res["bf16"][1][sample], ref["F"][sample]) < 1e-2
+    # BF16 against FP32 over all 98,304 atoms
+    assert rel_rmse(res["bf16"][1], res["fp32"][1]) < 1e-2
+    assert abs(res["bf16"][0][0] - res["fp32"][0][0]) / len(Z) < 1e-2
