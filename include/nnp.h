@@ -210,6 +210,38 @@ typedef enum {
 nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_t capacity_bytes,
                            int64_t* elems, int32_t* row_stride, hipStream_t stream);
 
+/*
+ * Per-stage timing with HIP events recorded on the call's stream around each
+ * stage of nnp_compute / nnp_compute_batch (used by the benchmark; see the
+ * paper's performance section for why per-step cost matters).  Stages:
+ */
+typedef enum {
+  NNP_STAGE_CELLS = 0,      /* binning, histogram, scan, stable scatter      */
+  NNP_STAGE_NEIGHBOURS = 1, /* neighbour lists                               */
+  NNP_STAGE_DESCRIPTOR = 2, /* descriptor forward                            */
+  NNP_STAGE_MM = 3,         /* MM potential channel forward                  */
+  NNP_STAGE_NETWORK = 4,    /* per-species networks, forward + backward      */
+  NNP_STAGE_ENERGY = 5,     /* FP64 energy reduction                         */
+  NNP_STAGE_ADJOINT = 6,    /* descriptor adjoint                            */
+  NNP_STAGE_GATHER = 7,     /* FP64 force gather                             */
+  NNP_STAGE_MM_ADJOINT = 8, /* MM channel adjoint                            */
+  NNP_STAGE_COUNT = 9
+} nnp_stage;
+
+/*
+ * max_calls > 0 enables timing for up to max_calls subsequent calls (events are
+ * created here, host-side); 0 disables it.  Either way the accumulated times
+ * are reset.  Not for use under graph capture.
+ */
+nnp_status nnp_profile_enable(nnp_model* m, int32_t max_calls);
+
+/*
+ * Synchronise `stream` and return, per stage, the summed event time in
+ * milliseconds over the recorded calls (ms_total[NNP_STAGE_COUNT]) and the
+ * number of recorded calls (*calls).
+ */
+nnp_status nnp_profile_read(nnp_model* m, double* ms_total, int64_t* calls, hipStream_t stream);
+
 /* Free the model, its weights and its workspace. */
 void nnp_destroy(nnp_model* m);
 

@@ -37,6 +37,10 @@ NNP_BUF_ATOM_ENERGY = 7
 NNP_BUF_DEDX = 8
 NNP_BUF_GRID = 9
 
+# nnp_stage
+STAGES = ["cells", "neighbours", "descriptor", "mm", "network", "energy", "adjoint", "gather", "mm_adjoint"]
+NNP_STAGE_COUNT = len(STAGES)
+
 
 class nnp_config(C.Structure):
     _fields_ = [
@@ -71,6 +75,8 @@ SIGNATURES = {
     "nnp_compute_batch": (C.c_int, [_P, C.c_int32, _I32P, _P, _I32P, _P, _P, _P]),
     "nnp_get_status": (C.c_int, [_P, _P]),
     "nnp_read_buffer": (C.c_int, [_P, C.c_int, _P, C.c_size_t, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),
+    "nnp_profile_enable": (C.c_int, [_P, C.c_int32]),
+    "nnp_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), _P]),
     "nnp_destroy": (None, [_P]),
     "nnp_status_string": (C.c_char_p, [C.c_int]),
     "nnp_last_error": (C.c_char_p, []),

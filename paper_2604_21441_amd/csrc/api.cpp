@@ -46,7 +46,8 @@ void free_workspace(nnp_model* m) {
   dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_key); dfree(m->d_bin_count);
   dfree(m->d_bin_start); dfree(m->d_cursor); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
   dfree(m->d_slot_atom); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
-  dfree(m->d_ang_off); dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
+  dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
+  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
   m->h_stage = nullptr;
   m->reserved = false;
@@ -175,6 +176,8 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
     for (int b = a; b < S; ++b) {
       p.pair_a[q] = a;
       p.pair_b[q] = b;
+      p.class_of[a][b] = q;
+      p.class_of[b][a] = q;
       ++q;
     }
 
@@ -209,6 +212,8 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   if (!m) return set_error(NNP_EINVAL, "null model");
   if (max_atoms < 1 || max_systems < 1 || max_mm < 0 || max_rad_nbr < 0 || max_ang_nbr < 0)
     return set_error(NNP_EINVAL, "capacities must be positive");
+  if (max_rad_nbr > 1024 || max_ang_nbr > 256)
+    return set_error(NNP_EINVAL, "neighbour capacities are limited to 1024 (radial) and 256 (angular)");
   HIP_TRY(hipDeviceSynchronize(), "nnp_reserve");
   free_workspace(m);
   m->max_atoms = max_atoms;
@@ -237,6 +242,11 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_nbr_ang, n * m->max_ang));
   chk(dalloc(&m->d_rad_off, n * (m->S + 1)));
   chk(dalloc(&m->d_ang_off, n * (m->S + 1)));
+  chk(dalloc(&m->d_angpos, n * m->max_ang));
+  chk(dalloc(&m->d_contrib, n * m->max_rad));
+  chk(dalloc(&m->d_self, 3 * n));
+  m->max_part = max_atoms / kTileAtoms + 2 * kMaxSpecies + 8;
+  chk(dalloc(&m->d_part, (size_t)m->max_part));
   chk(dalloc(&m->d_x, n * m->stride));
   chk(dalloc(&m->d_g, n * m->stride));
   chk(dalloc(&m->d_e, n));
@@ -291,24 +301,44 @@ nnp_status setup_periodic(nnp_model* m, const float* box) {
   return NNP_OK;
 }
 
+// Stage timing: event pair (start, stop) of stage `st` in the current call.
+struct StageTimer {
+  nnp_model* m;
+  hipStream_t s;
+  bool on;
+  StageTimer(nnp_model* mm, hipStream_t ss) : m(mm), s(ss), on(mm->prof_calls < mm->prof_max_calls) {}
+  void mark(int stage, int which) {
+    if (on) (void)hipEventRecord(m->prof_ev[((size_t)m->prof_calls * NNP_STAGE_COUNT + stage) * 2 + which], s);
+  }
+  void done() {
+    if (on) ++m->prof_calls;
+  }
+};
+
+#define STAGE(id, call, what)                          \
+  do {                                                 \
+    tm.mark(id, 0);                                    \
+    hipError_t e_ = (call);                            \
+    tm.mark(id, 1);                                    \
+    if (e_ != hipSuccess) return hip_error(e_, what);  \
+  } while (0)
+
 nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float* mm_pos, const float* mm_q,
                     double* energies, int n_sys, double* forces, double* mm_forces, int accumulate,
                     hipStream_t st) {
-  hipError_t e;
   m->last_n = n;
-  if ((e = launch_cells(*m, pos, n, st)) != hipSuccess) return hip_error(e, "cell list");
-  if ((e = launch_neighbours(*m, n, st)) != hipSuccess) return hip_error(e, "neighbours");
-  if ((e = launch_descriptor_fwd(*m, n, st)) != hipSuccess) return hip_error(e, "descriptor");
-  if (m->extra) {
-    if ((e = launch_mm_fwd(*m, n, n_mm, mm_pos, mm_q, st)) != hipSuccess) return hip_error(e, "mm channel");
-  }
-  if ((e = launch_mlp(*m, n, st)) != hipSuccess) return hip_error(e, "network");
-  if ((e = launch_energy(*m, n_sys, energies, accumulate, st)) != hipSuccess) return hip_error(e, "energy");
-  if ((e = launch_descriptor_bwd(*m, n, forces, st)) != hipSuccess) return hip_error(e, "descriptor adjoint");
-  if (m->extra) {
-    if ((e = launch_mm_bwd(*m, n, n_mm, mm_pos, mm_q, forces, mm_forces, st)) != hipSuccess)
-      return hip_error(e, "mm adjoint");
-  }
+  StageTimer tm(m, st);
+  STAGE(NNP_STAGE_CELLS, launch_cells(*m, pos, n, st), "cell list");
+  STAGE(NNP_STAGE_NEIGHBOURS, launch_neighbours(*m, n, st), "neighbours");
+  STAGE(NNP_STAGE_DESCRIPTOR, launch_descriptor_fwd(*m, n, st), "descriptor");
+  if (m->extra) STAGE(NNP_STAGE_MM, launch_mm_fwd(*m, n, n_mm, mm_pos, mm_q, st), "mm channel");
+  STAGE(NNP_STAGE_NETWORK, launch_mlp(*m, n, st), "network");
+  STAGE(NNP_STAGE_ENERGY, launch_energy(*m, n_sys, energies, accumulate, st), "energy");
+  STAGE(NNP_STAGE_ADJOINT, launch_descriptor_bwd(*m, n, st), "descriptor adjoint");
+  STAGE(NNP_STAGE_GATHER, launch_force_gather(*m, n, forces, st), "force gather");
+  if (m->extra)
+    STAGE(NNP_STAGE_MM_ADJOINT, launch_mm_bwd(*m, n, n_mm, mm_pos, mm_q, forces, mm_forces, st), "mm adjoint");
+  tm.done();
   return NNP_OK;
 }
 
@@ -509,8 +539,42 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
   return NNP_OK;
 }
 
+nnp_status nnp_profile_enable(nnp_model* m, int32_t max_calls) {
+  if (!m || max_calls < 0) return set_error(NNP_EINVAL, "bad argument");
+  for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);
+  m->prof_ev.clear();
+  m->prof_calls = 0;
+  m->prof_max_calls = 0;
+  if (max_calls == 0) return NNP_OK;
+  m->prof_ev.resize((size_t)max_calls * NNP_STAGE_COUNT * 2, nullptr);
+  for (auto& e : m->prof_ev) HIP_TRY(hipEventCreate(&e), "nnp_profile_enable");
+  m->prof_max_calls = max_calls;
+  return NNP_OK;
+}
+
+nnp_status nnp_profile_read(nnp_model* m, double* ms_total, int64_t* calls, hipStream_t stream) {
+  if (!m || !ms_total || !calls) return set_error(NNP_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(stream), "nnp_profile_read");
+  for (int st = 0; st < NNP_STAGE_COUNT; ++st) ms_total[st] = 0.0;
+  for (int c = 0; c < m->prof_calls; ++c)
+    for (int st = 0; st < NNP_STAGE_COUNT; ++st) {
+      hipEvent_t a = m->prof_ev[((size_t)c * NNP_STAGE_COUNT + st) * 2];
+      hipEvent_t b = m->prof_ev[((size_t)c * NNP_STAGE_COUNT + st) * 2 + 1];
+      float ms = 0.f;
+      // stages a call skipped have no recorded events: hipEventElapsedTime fails, count 0
+      if (hipEventQuery(a) == hipSuccess && hipEventQuery(b) == hipSuccess &&
+          hipEventElapsedTime(&ms, a, b) == hipSuccess)
+        ms_total[st] += ms;
+    }
+  *calls = m->prof_calls;
+  (void)hipGetLastError();
+  return NNP_OK;
+}
+
 void nnp_destroy(nnp_model* m) {
   if (!m) return;
+  for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);
+  m->prof_ev.clear();
   (void)hipDeviceSynchronize();
   free_workspace(m);
   if (m->d_wmat) (void)hipFree(m->d_wmat);

@@ -143,87 +143,144 @@ struct NeighArgs {
   float rc2, rca2;
   int* rad;
   int* ang;
+  int* angpos;
   int* rad_off;
   int* ang_off;
   int max_rad, max_ang;
   int* status;
 };
 
-// One thread per sorted slot; candidates are scanned species by species so
-// each list comes out grouped by species.
-__global__ __launch_bounds__(kBlock) void k_neighbours(NeighArgs a, Geometry g) {
+constexpr int kMaxStencil = 27;
+
+// One wavefront per sorted slot i.  For each species, the candidate atoms of
+// the (deduplicated) 27-cell stencil are visited in ascending cell order --
+// hence ascending slot order -- one candidate per lane, and the accepted ones
+// are compacted with a ballot, so every species segment of a list is sorted
+// by slot.  Angular neighbours (r < rc_ang) also record their position in
+// the radial list.  Lists never hold more than their capacity; an overflow
+// sets the device status word.
+__global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
 #pragma clang fp contract(off)
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  float4 pi = a.spos[i];
-  int bin = a.key[a.perm[i]] % g.n_bins;
-  int c[3] = {0, 0, 0};
-  int nd[3] = {1, 1, 1};
-  int offs[3][3];
+  __shared__ int s_cell[kMaxStencil];
+  __shared__ int s_start[kMaxStencil];
+  __shared__ int s_off[kMaxStencil];
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const float4 pi = a.spos[i];
+  const int bin = a.key[a.perm[i]] % g.n_bins;
+  int nst = 1;
+  int my_cell = -1;
   if (g.periodic) {
+    int c[3], nd[3];
     c[0] = bin / (g.nc[1] * g.nc[2]);
     c[1] = (bin / g.nc[2]) % g.nc[1];
     c[2] = bin % g.nc[2];
-    for (int k = 0; k < 3; ++k) {
-      if (g.nc[k] >= 3) {
-        nd[k] = 3; offs[k][0] = -1; offs[k][1] = 0; offs[k][2] = 1;
-      } else if (g.nc[k] == 2) {
-        nd[k] = 2; offs[k][0] = 0; offs[k][1] = 1;
-      } else {
-        nd[k] = 1; offs[k][0] = 0;
+    for (int k = 0; k < 3; ++k) nd[k] = g.nc[k] >= 3 ? 3 : g.nc[k];
+    nst = nd[0] * nd[1] * nd[2];
+    if (lane < nst) {
+      int o[3] = {lane / (nd[1] * nd[2]), (lane / nd[2]) % nd[1], lane % nd[2]};
+      int w[3];
+      for (int k = 0; k < 3; ++k) {
+        // offsets {-1, 0, 1} for >= 3 cells, {0, 1} for 2 cells, {0} for 1 cell
+        int off = nd[k] == 3 ? o[k] - 1 : o[k];
+        int x = c[k] + off;
+        w[k] = x < 0 ? x + g.nc[k] : (x >= g.nc[k] ? x - g.nc[k] : x);
       }
+      my_cell = (w[0] * g.nc[1] + w[1]) * g.nc[2] + w[2];
     }
-  } else {
-    offs[0][0] = offs[1][0] = offs[2][0] = 0;
+  } else if (lane == 0) {
+    my_cell = bin;
   }
+  // ascending order of the stencil cells (their ids are distinct)
+  int rank = 0;
+  for (int l = 0; l < nst; ++l) {
+    int o = __shfl(my_cell, l, 64);
+    rank += (o < my_cell) ? 1 : 0;
+  }
+  if (lane < nst) s_cell[rank] = my_cell;
+  __syncthreads();
+
   int* rad = a.rad + (int64_t)i * a.max_rad;
   int* ang = a.ang + (int64_t)i * a.max_ang;
+  int* angpos = a.angpos + (int64_t)i * a.max_ang;
+  const uint64_t lt = __lanemask_lt();
   int nr = 0, na = 0;
+  bool overflow = false;
   for (int s = 0; s < a.S; ++s) {
-    a.rad_off[(int64_t)i * (a.S + 1) + s] = min(nr, a.max_rad);
-    a.ang_off[(int64_t)i * (a.S + 1) + s] = min(na, a.max_ang);
-    for (int ox = 0; ox < nd[0]; ++ox)
-      for (int oy = 0; oy < nd[1]; ++oy)
-        for (int oz = 0; oz < nd[2]; ++oz) {
-          int cb;
-          if (g.periodic) {
-            int x = c[0] + offs[0][ox]; x = x < 0 ? x + g.nc[0] : (x >= g.nc[0] ? x - g.nc[0] : x);
-            int y = c[1] + offs[1][oy]; y = y < 0 ? y + g.nc[1] : (y >= g.nc[1] ? y - g.nc[1] : y);
-            int z = c[2] + offs[2][oz]; z = z < 0 ? z + g.nc[2] : (z >= g.nc[2] ? z - g.nc[2] : z);
-            cb = (x * g.nc[1] + y) * g.nc[2] + z;
-          } else {
-            cb = bin;
-          }
-          int k = s * g.n_bins + cb;
-          int j0 = a.bin_start[k], j1 = a.bin_start[k + 1];
-          for (int j = j0; j < j1; ++j) {
-            if (j == i) continue;
-            float4 pj = a.spos[j];
-            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-            if (g.periodic) {
-              float sx = rintf(dx * g.inv_box[0]);
-              float sy = rintf(dy * g.inv_box[1]);
-              float sz = rintf(dz * g.inv_box[2]);
-              float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-              dx = dx - tx; dy = dy - ty; dz = dz - tz;
-            }
-            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-            float r2 = xx + yy;
-            r2 = r2 + zz;
-            if (r2 < a.rc2) {
-              if (nr < a.max_rad) rad[nr] = j;
-              ++nr;
-              if (r2 < a.rca2) {
-                if (na < a.max_ang) ang[na] = j;
-                ++na;
-              }
-            }
-          }
+    if (lane == 0) {
+      a.rad_off[(int64_t)i * (a.S + 1) + s] = nr;
+      a.ang_off[(int64_t)i * (a.S + 1) + s] = na;
+    }
+    int st = 0, cnt = 0;
+    if (lane < nst) {
+      int b = s * g.n_bins + s_cell[lane];
+      st = a.bin_start[b];
+      cnt = a.bin_start[b + 1] - st;
+    }
+    int inc = cnt;
+    for (int off = 1; off < 32; off <<= 1) {
+      int v = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += v;
+    }
+    const int total = __shfl(inc, nst - 1, 64);
+    if (lane < nst) {
+      s_start[lane] = st;
+      s_off[lane] = inc - cnt;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool in_r = false, in_a = false;
+      int j = -1;
+      if (c < total) {
+        int lo = 0, hi = nst - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
         }
+        j = s_start[lo] + (c - s_off[lo]);
+        if (j != i) {
+          float4 pj = a.spos[j];
+          float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+          if (g.periodic) {
+            float sx = rintf(dx * g.inv_box[0]);
+            float sy = rintf(dy * g.inv_box[1]);
+            float sz = rintf(dz * g.inv_box[2]);
+            float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+            dx = dx - tx; dy = dy - ty; dz = dz - tz;
+          }
+          float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+          float r2 = xx + yy;
+          r2 = r2 + zz;
+          in_r = r2 < a.rc2;
+          in_a = r2 < a.rca2;
+        }
+      }
+      const uint64_t mr = __ballot(in_r);
+      const int pr = nr + __popcll(mr & lt);
+      const bool in_a2 = in_a && pr < a.max_rad;   // angular entries point into the radial list
+      const uint64_t ma = __ballot(in_a2);
+      const int pa = na + __popcll(ma & lt);
+      if (in_r && pr < a.max_rad) rad[pr] = j;
+      if (in_a2 && pa < a.max_ang) {
+        ang[pa] = j;
+        angpos[pa] = pr;
+      }
+      nr += __popcll(mr);
+      na += __popcll(ma);
+      if (nr > a.max_rad || na > a.max_ang) {
+        overflow = true;
+        nr = min(nr, a.max_rad);
+        na = min(na, a.max_ang);
+      }
+    }
+    __syncthreads();
   }
-  a.rad_off[(int64_t)i * (a.S + 1) + a.S] = min(nr, a.max_rad);
-  a.ang_off[(int64_t)i * (a.S + 1) + a.S] = min(na, a.max_ang);
-  if (nr > a.max_rad || na > a.max_ang) atomicOr(a.status, kStatusCapacity);
+  if (lane == 0) {
+    a.rad_off[(int64_t)i * (a.S + 1) + a.S] = nr;
+    a.ang_off[(int64_t)i * (a.S + 1) + a.S] = na;
+    if (overflow) atomicOr(a.status, kStatusCapacity);
+  }
 }
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -267,12 +324,13 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   a.rca2 = m.dp.rc_ang * m.dp.rc_ang;
   a.rad = m.d_nbr_rad;
   a.ang = m.d_nbr_ang;
+  a.angpos = m.d_angpos;
   a.rad_off = m.d_rad_off;
   a.ang_off = m.d_ang_off;
   a.max_rad = m.max_rad;
   a.max_ang = m.max_ang;
   a.status = m.d_status;
-  hipLaunchKernelGGL(k_neighbours, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, a, m.geo);
+  hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);
   return hipGetLastError();
 }
 

@@ -158,143 +158,221 @@ __global__ __launch_bounds__(kBlock) void k_desc_fwd(DescArgs a, DescParams p, G
   for (int m = 0; m < kAngShifts; ++m) o4[m] = make_float4(acc[m][0], acc[m][1], acc[m][2], acc[m][3]);
 }
 
-__device__ __forceinline__ void add_force(double* f, int atom, double x, double y, double z) {
-  double* p = f + 3 * (int64_t)atom;
-  unsafeAtomicAdd(p + 0, x);
-  unsafeAtomicAdd(p + 1, y);
-  unsafeAtomicAdd(p + 2, z);
+// Adjoint, one wavefront per centre atom i (no global atomics).
+//
+// E depends on d_ij = x_j - x_i, so a pair vector v = dE/d(d_ij) contributes
+// -v to F_j and +v to F_i.  The wavefront
+//   1. evaluates the radial terms, one neighbour per lane, storing v in an
+//      FP64 LDS slot per radial neighbour;
+//   2. caches the geometry of the angular neighbours in LDS;
+//   3. evaluates the angular triplets (j < k), one per lane, adding v_j and
+//      v_k into the neighbours' slots with FP64 LDS atomics;
+//   4. hands each neighbour's total to that neighbour: the centre's position
+//      in the neighbour's own list (lists are symmetric and sorted by slot
+//      within each species segment) is found by binary search, and the
+//      total, rounded once to FP32, is stored there -- each entry has exactly
+//      one writer;
+//   5. stores the centre's own total (FP64).
+// k_force_gather then sums, per atom and in FP64, its own total and the
+// entries of its list, and adds the result to the caller's force array.
+struct BwdArgs {
+  const float4* spos;
+  const int* rad;
+  const int* ang;
+  const int* angpos;
+  const int* rad_off;
+  const int* ang_off;
+  int max_rad, max_ang, n;
+  const float* g;
+  float4* contrib;   // [n][max_rad]
+  double* self;      // [n][3]
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
-// Adjoint: g = dE/dx per atom -> dE/d(d_ij) per neighbour pair -> forces.
-// E depends on d_ij = x_j - x_i, so a pair vector v = dE/d(d_ij) gives
-// F_j -= v and F_i += v.  The centre's total and each outer neighbour's total
-// are accumulated in FP64 registers before one atomic add; inner neighbours
-// of the angular double loop are added per pair.
-__global__ __launch_bounds__(kBlock) void k_desc_bwd(DescArgs a, DescParams p, Geometry geo) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  int blk = gid / a.n;
-  int i = gid - blk * a.n;
-  if (blk >= p.S + p.P) return;
+__global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geometry geo) {
+  extern __shared__ double smem_d[];
+  double* slot = smem_d;                                          // [max_rad][3]
+  float* gang = reinterpret_cast<float*>(slot + 3 * a.max_rad);   // [max_ang][8]
+  int* rpos = reinterpret_cast<int*>(gang + 8 * a.max_ang);       // [max_ang]
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
   const int S1 = p.S + 1;
+  const int nr = a.rad_off[(int64_t)i * S1 + p.S];
+  const int na = a.ang_off[(int64_t)i * S1 + p.S];
+  const int* rrow = a.rad + (int64_t)i * a.max_rad;
+  const int* arow = a.ang + (int64_t)i * a.max_ang;
   const float* gi = a.g + (int64_t)i * p.stride;
-  double fix = 0.0, fiy = 0.0, fiz = 0.0;
-  if (blk < p.S) {
-    const int* row = a.rad + (int64_t)i * a.max_rad;
-    int j0 = a.rad_off[(int64_t)i * S1 + blk], j1 = a.rad_off[(int64_t)i * S1 + blk + 1];
-    float gk[kRadShifts];
-    const float4* g4 = reinterpret_cast<const float4*>(gi + blk * kRadShifts);
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+
+  // 1. radial pairs
+  for (int t = lane; t < nr; t += 64) {
+    const float4 pj = a.spos[rrow[t]];
+    const int sj = __float_as_int(pj.w);
+    Geo d = displacement(pi, pj, geo);
+    float arg = d.r * c.inv2rc;
+    float fc = 0.5f * cos_rev(arg) + 0.5f;
+    float dfc = c.dfc_r * sin_rev(arg);
+    const float4* g4 = reinterpret_cast<const float4*>(gi + sj * kRadShifts);
+    float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-    for (int k = 0; k < kRadShifts / 4; ++k) {
-      float4 v = g4[k];
-      gk[4 * k] = v.x; gk[4 * k + 1] = v.y; gk[4 * k + 2] = v.z; gk[4 * k + 3] = v.w;
-    }
-    for (int jj = j0; jj < j1; ++jj) {
-      int j = row[jj];
-      Geo d = displacement(pi, a.spos[j], geo);
-      float arg = d.r * c.inv2rc;
-      float fc = 0.5f * cos_rev(arg) + 0.5f;
-      float dfc = c.dfc_r * sin_rev(arg);
-      float s0 = 0.f, s1 = 0.f;
+    for (int q = 0; q < kRadShifts / 4; ++q) {
+      float4 gv = g4[q];
+      float gk[4] = {gv.x, gv.y, gv.z, gv.w};
 #pragma unroll
-      for (int k = 0; k < kRadShifts; ++k) {
-        float t = d.r - p.rad_shift[k];
-        float B = gk[k] * ex2(-c.eta_r_l2 * t * t);
+      for (int u = 0; u < 4; ++u) {
+        float tt = d.r - p.rad_shift[4 * q + u];
+        float B = gk[u] * ex2(-c.eta_r_l2 * tt * tt);
         s0 += B;
-        s1 += B * t;
+        s1 += B * tt;
       }
-      float dTdr = dfc * s0 - 2.f * p.eta_rad * fc * s1;
-      float w = dTdr * d.ir;
-      float vx = w * d.dx, vy = w * d.dy, vz = w * d.dz;
-      add_force(a.forces, a.slot_atom[j], -(double)vx, -(double)vy, -(double)vz);
-      fix += vx; fiy += vy; fiz += vz;
     }
-    add_force(a.forces, a.slot_atom[i], fix, fiy, fiz);
-    return;
+    float dTdr = dfc * s0 - 2.f * p.eta_rad * fc * s1;
+    float w = dTdr * d.ir;
+    float vx = w * d.dx, vy = w * d.dy, vz = w * d.dz;
+    slot[3 * t + 0] = vx;
+    slot[3 * t + 1] = vy;
+    slot[3 * t + 2] = vz;
+    fx += vx; fy += vy; fz += vz;
   }
-  const int q = blk - p.S;
-  const int sa = p.pair_a[q], sb = p.pair_b[q];
-  const int* row = a.ang + (int64_t)i * a.max_ang;
-  const int a0 = a.ang_off[(int64_t)i * S1 + sa], a1 = a.ang_off[(int64_t)i * S1 + sa + 1];
-  const int b0 = a.ang_off[(int64_t)i * S1 + sb], b1 = a.ang_off[(int64_t)i * S1 + sb + 1];
-  float G[kAngShifts][kAngSects];
-  const float4* g4 = reinterpret_cast<const float4*>(gi + p.S * kRadShifts + q * kAngShifts * kAngSects);
+  // 2. angular neighbour geometry
+  for (int u = lane; u < na; u += 64) {
+    const float4 pj = a.spos[arow[u]];
+    Geo d = displacement(pi, pj, geo);
+    float arg = d.r * c.inv2rca;
+    float* o = gang + 8 * u;
+    o[0] = d.dx * d.ir; o[1] = d.dy * d.ir; o[2] = d.dz * d.ir;
+    o[3] = d.r; o[4] = d.ir;
+    o[5] = 0.5f * cos_rev(arg) + 0.5f;
+    o[6] = c.dfc_a * sin_rev(arg);
+    o[7] = pj.w;
+    rpos[u] = a.angpos[(int64_t)i * a.max_ang + u];
+  }
+  __syncthreads();
+  // 3. angular triplets, j < k in the angular list
+  const int T = na * (na - 1) / 2;
+  for (int t = lane; t < T; t += 64) {
+    int b = (int)((1.f + __builtin_amdgcn_sqrtf(1.f + 8.f * (float)t)) * 0.5f);
+    while (b * (b - 1) / 2 > t) --b;
+    while ((b + 1) * b / 2 <= t) ++b;
+    const int aj = t - b * (b - 1) / 2;
+    const float* oj = gang + 8 * aj;
+    const float* ok = gang + 8 * b;
+    const float ujx = oj[0], ujy = oj[1], ujz = oj[2], rj = oj[3], irj = oj[4], fcj = oj[5], dfcj = oj[6];
+    const float ukx = ok[0], uky = ok[1], ukz = ok[2], rk = ok[3], irk = ok[4], fck = ok[5], dfck = ok[6];
+    const int sj = __float_as_int(oj[7]), sk = __float_as_int(ok[7]);
+    const int q = p.class_of[sj][sk];
+    const float4* g4 = reinterpret_cast<const float4*>(gi + p.S * kRadShifts + q * kAngShifts * kAngSects);
+    float cs = ujx * ukx + ujy * uky + ujz * ukz;
+    float ct = 0.95f * cs;
+    float st = __builtin_amdgcn_sqrtf(1.f - ct * ct);
+    float ist = __builtin_amdgcn_rcpf(st);
+    float rbar = 0.5f * (rj + rk);
+    float A[kAngSects], dA[kAngSects];
 #pragma unroll
-  for (int m = 0; m < kAngShifts; ++m) {
-    float4 v = g4[m];
-    G[m][0] = v.x; G[m][1] = v.y; G[m][2] = v.z; G[m][3] = v.w;
-  }
-  for (int jj = a0; jj < a1; ++jj) {
-    int j = row[jj];
-    Geo dj = displacement(pi, a.spos[j], geo);
-    float argj = dj.r * c.inv2rca;
-    float fcj = 0.5f * cos_rev(argj) + 0.5f;
-    float dfcj = c.dfc_a * sin_rev(argj);
-    float ujx = dj.dx * dj.ir, ujy = dj.dy * dj.ir, ujz = dj.dz * dj.ir;
-    double fjx = 0.0, fjy = 0.0, fjz = 0.0;
-    for (int kk = (sa == sb ? jj + 1 : b0); kk < b1; ++kk) {
-      int k = row[kk];
-      Geo dk = displacement(pi, a.spos[k], geo);
-      float argk = dk.r * c.inv2rca;
-      float fck = 0.5f * cos_rev(argk) + 0.5f;
-      float dfck = c.dfc_a * sin_rev(argk);
-      float ukx = dk.dx * dk.ir, uky = dk.dy * dk.ir, ukz = dk.dz * dk.ir;
-      float cs = ujx * ukx + ujy * uky + ujz * ukz;
-      float ct = 0.95f * cs;
-      float st = __builtin_amdgcn_sqrtf(1.f - ct * ct);
-      float ist = __builtin_amdgcn_rcpf(st);
-      float rbar = 0.5f * (dj.r + dk.r);
-      float A[kAngSects], dA[kAngSects];
+    for (int n = 0; n < kAngSects; ++n) {
+      float base = 1.f + ct * p.cos_sect[n] + st * p.sin_sect[n];
+      float An = ex2(p.zeta * lg2(base));
+      A[n] = An;
+      dA[n] = p.zeta * An * __builtin_amdgcn_rcpf(base) * 0.95f * (p.cos_sect[n] - ct * ist * p.sin_sect[n]);
+    }
+    float h[kAngSects] = {0.f, 0.f, 0.f, 0.f};
+    float sdr = 0.f;
+#pragma unroll
+    for (int m = 0; m < kAngShifts; ++m) {
+      float4 gv = g4[m];
+      float G[4] = {gv.x, gv.y, gv.z, gv.w};
+      float tt = rbar - p.ang_shift[m];
+      float B = ex2(-c.eta_a_l2 * tt * tt);
+      float km = 0.f;
 #pragma unroll
       for (int n = 0; n < kAngSects; ++n) {
-        float base = 1.f + ct * p.cos_sect[n] + st * p.sin_sect[n];
-        float An = ex2(p.zeta * lg2(base));
-        A[n] = An;
-        // d/dc of (1 + cos(theta' - theta_n))^zeta
-        dA[n] = p.zeta * An * __builtin_amdgcn_rcpf(base) * 0.95f * (p.cos_sect[n] - ct * ist * p.sin_sect[n]);
+        h[n] += G[n] * B;
+        km += G[n] * A[n];
       }
-      float h[kAngSects] = {0.f, 0.f, 0.f, 0.f};
-      float sdr = 0.f;   // sum_m dB_m/drbar * sum_n G[m][n] A_n
-#pragma unroll
-      for (int m = 0; m < kAngShifts; ++m) {
-        float t = rbar - p.ang_shift[m];
-        float B = ex2(-c.eta_a_l2 * t * t);
-        float km = 0.f;
-#pragma unroll
-        for (int n = 0; n < kAngSects; ++n) {
-          h[n] += G[m][n] * B;
-          km += G[m][n] * A[n];
-        }
-        sdr += -2.f * p.eta_ang * t * B * km;
-      }
-      float SA = 0.f, SdA = 0.f;
-#pragma unroll
-      for (int n = 0; n < kAngSects; ++n) {
-        SA += h[n] * A[n];
-        SdA += h[n] * dA[n];
-      }
-      float F = p.ang_pref * fcj * fck;
-      float dTdc = F * SdA;
-      float dTdrbar = F * sdr;
-      float dTdrj = 0.5f * dTdrbar + p.ang_pref * dfcj * fck * SA;
-      float dTdrk = 0.5f * dTdrbar + p.ang_pref * fcj * dfck * SA;
-      float cj = dTdc * dj.ir, ck = dTdc * dk.ir;
-      float vjx = cj * (ukx - cs * ujx) + dTdrj * ujx;
-      float vjy = cj * (uky - cs * ujy) + dTdrj * ujy;
-      float vjz = cj * (ukz - cs * ujz) + dTdrj * ujz;
-      float vkx = ck * (ujx - cs * ukx) + dTdrk * ukx;
-      float vky = ck * (ujy - cs * uky) + dTdrk * uky;
-      float vkz = ck * (ujz - cs * ukz) + dTdrk * ukz;
-      add_force(a.forces, a.slot_atom[k], -(double)vkx, -(double)vky, -(double)vkz);
-      fjx += vjx; fjy += vjy; fjz += vjz;
-      fix += (double)vjx + (double)vkx;
-      fiy += (double)vjy + (double)vky;
-      fiz += (double)vjz + (double)vkz;
+      sdr += -2.f * p.eta_ang * tt * B * km;
     }
-    if (fjx != 0.0 || fjy != 0.0 || fjz != 0.0) add_force(a.forces, a.slot_atom[j], -fjx, -fjy, -fjz);
+    float SA = 0.f, SdA = 0.f;
+#pragma unroll
+    for (int n = 0; n < kAngSects; ++n) {
+      SA += h[n] * A[n];
+      SdA += h[n] * dA[n];
+    }
+    float F = p.ang_pref * fcj * fck;
+    float dTdc = F * SdA;
+    float dTdrbar = F * sdr;
+    float dTdrj = 0.5f * dTdrbar + p.ang_pref * dfcj * fck * SA;
+    float dTdrk = 0.5f * dTdrbar + p.ang_pref * fcj * dfck * SA;
+    float cj = dTdc * irj, ck = dTdc * irk;
+    float vjx = cj * (ukx - cs * ujx) + dTdrj * ujx;
+    float vjy = cj * (uky - cs * ujy) + dTdrj * ujy;
+    float vjz = cj * (ukz - cs * ujz) + dTdrj * ujz;
+    float vkx = ck * (ujx - cs * ukx) + dTdrk * ukx;
+    float vky = ck * (ujy - cs * uky) + dTdrk * uky;
+    float vkz = ck * (ujz - cs * ukz) + dTdrk * ukz;
+    double* sjp = slot + 3 * rpos[aj];
+    double* skp = slot + 3 * rpos[b];
+    unsafeAtomicAdd(sjp + 0, (double)vjx);
+    unsafeAtomicAdd(sjp + 1, (double)vjy);
+    unsafeAtomicAdd(sjp + 2, (double)vjz);
+    unsafeAtomicAdd(skp + 0, (double)vkx);
+    unsafeAtomicAdd(skp + 1, (double)vky);
+    unsafeAtomicAdd(skp + 2, (double)vkz);
+    fx += (double)vjx + (double)vkx;
+    fy += (double)vjy + (double)vky;
+    fz += (double)vjz + (double)vkz;
   }
-  add_force(a.forces, a.slot_atom[i], fix, fiy, fiz);
+  __syncthreads();
+  // 4. each neighbour's total goes to the centre's slot in the neighbour's list
+  const int si = __float_as_int(pi.w);
+  for (int t = lane; t < nr; t += 64) {
+    const int j = rrow[t];
+    const int* jrow = a.rad + (int64_t)j * a.max_rad;
+    int lo = a.rad_off[(int64_t)j * S1 + si], hi = a.rad_off[(int64_t)j * S1 + si + 1] - 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (jrow[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    if (lo <= hi && jrow[lo] == i)
+      a.contrib[(int64_t)j * a.max_rad + lo] =
+          make_float4((float)-slot[3 * t], (float)-slot[3 * t + 1], (float)-slot[3 * t + 2], 0.f);
+  }
+  // 5. the centre's own total
+  fx = wave_sum_d(fx);
+  fy = wave_sum_d(fy);
+  fz = wave_sum_d(fz);
+  if (lane == 0) {
+    a.self[3 * (int64_t)i + 0] = fx;
+    a.self[3 * (int64_t)i + 1] = fy;
+    a.self[3 * (int64_t)i + 2] = fz;
+  }
+}
+
+// F_atom += self + sum over the atom's radial list entries (FP64), one thread per atom.
+__global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ contrib,
+                                                         const double* __restrict__ self,
+                                                         const int* __restrict__ rad_off,
+                                                         const int* __restrict__ slot_atom, int n, int S,
+                                                         int max_rad, double* __restrict__ forces) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nr = rad_off[(int64_t)i * (S + 1) + S];
+  double fx = self[3 * (int64_t)i], fy = self[3 * (int64_t)i + 1], fz = self[3 * (int64_t)i + 2];
+  const float4* row = contrib + (int64_t)i * max_rad;
+  for (int t = 0; t < nr; ++t) {
+    float4 v = row[t];
+    fx += v.x; fy += v.y; fz += v.z;
+  }
+  double* f = forces + 3 * (int64_t)slot_atom[i];
+  f[0] += fx;
+  f[1] += fy;
+  f[2] += fz;
 }
 
 DescArgs make_args(nnp_model& m, int n) {
@@ -325,13 +403,31 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_descriptor_bwd(nnp_model& m, int n, double* forces, hipStream_t st) {
+hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  DescArgs a = make_args(m, n);
-  a.forces = forces;
-  int64_t lanes = (int64_t)(m.S + m.P) * n;
-  hipLaunchKernelGGL(k_desc_bwd, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                     a, m.dp, m.geo);
+  BwdArgs a;
+  a.spos = m.d_spos;
+  a.rad = m.d_nbr_rad;
+  a.ang = m.d_nbr_ang;
+  a.angpos = m.d_angpos;
+  a.rad_off = m.d_rad_off;
+  a.ang_off = m.d_ang_off;
+  a.max_rad = m.max_rad;
+  a.max_ang = m.max_ang;
+  a.n = n;
+  a.g = m.d_g;
+  a.contrib = m.d_contrib;
+  a.self = m.d_self;
+  size_t lds = sizeof(double) * 3 * (size_t)m.max_rad + sizeof(float) * 8 * (size_t)m.max_ang +
+               sizeof(int) * (size_t)m.max_ang;
+  hipLaunchKernelGGL(k_desc_bwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_gather(nnp_model& m, int n, double* forces, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_force_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_contrib, m.d_self,
+                     m.d_rad_off, m.d_slot_atom, n, m.S, m.max_rad, forces);
   return hipGetLastError();
 }
 

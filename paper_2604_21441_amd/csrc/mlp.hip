@@ -258,7 +258,38 @@ __global__ __launch_bounds__(kBlock) void k_mlp(MlpArgs a, float alpha) {
       }
     }
   }
-  if (valid && q == 0) a.e[row] = e_sum / (float)a.n_members;
+  const float e_atom = e_sum / (float)a.n_members;
+  if (valid && q == 0) a.e[row] = e_atom;
+  if (a.part != nullptr) {
+    double ev = (valid && q == 0) ? (double)e_atom : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ev += __shfl_xor(ev, off, 64);
+    if (lane == 0) a.part[wave] = ev;
+  }
+}
+
+// Single-system energy: sum of the per-wavefront partials in a fixed order.
+constexpr int kFin = 256;
+__global__ __launch_bounds__(kFin) void k_energy_final(const double* __restrict__ part,
+                                                       const int* __restrict__ bin_start, int n_bins, int S,
+                                                       double* __restrict__ out, int accumulate,
+                                                       int* __restrict__ status) {
+  __shared__ double red[kFin];
+  int tiles = 0;
+  for (int s = 0; s < S; ++s) tiles += (bin_start[(s + 1) * n_bins] - bin_start[s * n_bins] + 15) >> 4;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < tiles; t += kFin) acc += part[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kFin / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    if (!isfinite(v)) atomicOr(status, kStatusNonFinite);
+    out[0] = accumulate ? out[0] + v : v;
+  }
 }
 
 // Per-system FP64 energy: a fixed-order block reduction (deterministic).
@@ -318,6 +349,7 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.mat_per_species = m.mat_per_species;
   a.vec_per_species = m.vec_per_species;
   a.status = m.d_status;
+  a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
   switch (m.net_kind) {
     case 0:
@@ -332,10 +364,13 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
 }
 
 hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st) {
-  int single = m.geo.periodic || n_sys == 1 ? 1 : 0;
-  int blocks = single ? 1 : n_sys;
-  hipLaunchKernelGGL(k_energy, dim3(blocks), dim3(kRed), 0, st, m.d_e, m.d_bin_start, m.geo.n_bins, m.S, single,
-                     energies, accumulate, m.d_status);
+  if (m.geo.periodic || m.geo.n_bins == 1) {
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kFin), 0, st, m.d_part, m.d_bin_start, m.geo.n_bins, m.S,
+                       energies, accumulate, m.d_status);
+  } else {
+    hipLaunchKernelGGL(k_energy, dim3(n_sys), dim3(kRed), 0, st, m.d_e, m.d_bin_start, m.geo.n_bins, m.S, 0,
+                       energies, accumulate, m.d_status);
+  }
   return hipGetLastError();
 }
 

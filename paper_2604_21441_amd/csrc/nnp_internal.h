@@ -35,6 +35,7 @@ struct DescParams {
   int S, P, D, stride;                  // species, pair classes, descriptor length, row stride
   int extra;                            // 1 if the MM potential is the last input
   int pair_a[kMaxPairs], pair_b[kMaxPairs];
+  int class_of[kMaxSpecies][kMaxSpecies];  // unordered species pair -> class
 };
 
 // Geometry of the current call.
@@ -66,6 +67,7 @@ struct MlpArgs {
   int n_bins, S, n_members, stride;
   int64_t mat_per_species; // elements per (member, species) in wmat
   int64_t vec_per_species; // elements per (member, species) in wvec
+  double* part;            // per-wavefront FP64 energy partials, or null
   int* status;
 };
 
@@ -108,6 +110,11 @@ struct nnp_model {
   int* d_nbr_ang = nullptr;
   int* d_rad_off = nullptr;
   int* d_ang_off = nullptr;
+  int* d_angpos = nullptr;     // [n][max_ang] position of each angular neighbour in the radial list
+  float4* d_contrib = nullptr; // [n][max_rad] force on atom i from the centre at its radial slot
+  double* d_self = nullptr;    // [n][3] force on each atom from its own environment
+  double* d_part = nullptr;    // per-wavefront FP64 energy partials
+  int max_part = 0;
   float* d_x = nullptr;
   float* d_g = nullptr;
   float* d_e = nullptr;
@@ -120,6 +127,10 @@ struct nnp_model {
   int topo_n_atoms = -1;
   std::vector<int> topo_Z, topo_idx, topo_offsets;
   int n_nnp = 0;
+
+  // stage timing
+  std::vector<hipEvent_t> prof_ev;   // [call][stage][2]
+  int prof_max_calls = 0, prof_calls = 0;
 
   // last call
   nnp::Geometry geo{};
@@ -144,7 +155,8 @@ hipError_t launch_neighbours(nnp_model& m, int n_nnp, hipStream_t st);
 
 // descriptor.hip
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st);
-hipError_t launch_descriptor_bwd(nnp_model& m, int n, double* forces, hipStream_t st);
+hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st);
+hipError_t launch_force_gather(nnp_model& m, int n, double* forces, hipStream_t st);
 
 // mm.hip
 hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,

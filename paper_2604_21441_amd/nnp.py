@@ -18,7 +18,7 @@ from . import _lib as L
 
 __all__ = [
     "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
-    "nnp_read_buffer", "nnp_destroy", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
 
@@ -160,6 +160,18 @@ def nnp_read_buffer(h, which: int, stream=None) -> np.ndarray:
     if stride.value > 1:
         out = out.reshape(-1, stride.value)
     return out
+
+
+def nnp_profile_enable(h, max_calls: int) -> None:
+    _check(L.load().nnp_profile_enable(h, int(max_calls)), "nnp_profile_enable")
+
+
+def nnp_profile_read(h, stream=None) -> tuple[dict, int]:
+    """Summed per-stage event times (ms) over the recorded calls, and the call count."""
+    ms = (C.c_double * L.NNP_STAGE_COUNT)()
+    calls = C.c_int64()
+    _check(L.load().nnp_profile_read(h, ms, C.byref(calls), _stream(stream)), "nnp_profile_read")
+    return {name: ms[k] for k, name in enumerate(L.STAGES)}, calls.value
 
 
 def nnp_destroy(h) -> None:
