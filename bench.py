@@ -5,7 +5,9 @@ One step is one full energy + force evaluation through the C ABI
 (``nnp_compute``): cell list, neighbour lists, descriptors, per-species
 networks (forward + backward), FP64 energy sum, descriptor adjoint and FP64
 force gather.  The neighbour search reruns every step; inputs stay resident
-in device memory.
+in device memory.  The timed steps use the library's production path (one
+HIP-graph replay per step); a second pass of the same length with per-stage
+HIP events gives the kernel durations used for the roofline entry.
 
 Default workload: periodic water box, 4,096 molecules (12,288 atoms,
 L = 49.7 A), the FP32 form; the BF16 form is timed on the same input and both
@@ -79,7 +81,9 @@ def build_inputs(name):
     return cfg, dict(pos=pos, Z=Z, box=None, offsets=np.asarray(off, np.int32))
 
 
-def run_form(P, cfg, flat, inp, prec, steps, warmup):
+def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
+    """Time `steps` production calls (HIP-graph replay, preallocated outputs, topology
+    reused), then the same number of calls with per-stage HIP-event timing."""
     import numpy as np
     import torch
     m = P.NNPModel(cfg, weights=flat, precision=prec)
@@ -87,37 +91,57 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup):
     n = d.shape[0]
     batched = inp["offsets"] is not None
     if batched:
-        m.reserve(n, len(inp["offsets"]) - 1)
-        call = lambda: m.compute_batch(d, inp["Z"], inp["offsets"])
+        n_sys = len(inp["offsets"]) - 1
+        m.reserve(n, n_sys)
+        E = torch.empty(n_sys, dtype=torch.float64, device="cuda")
+        F = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        first = lambda: m.compute_batch(d, inp["Z"], inp["offsets"], out=(E, F))
+        call = lambda: m.compute_batch(d, None, inp["offsets"], out=(E, F))
     else:
         m.reserve(n)
-        call = lambda: m.compute(d, inp["Z"], inp["box"])
-    E, F = call()[:2]
+        E = torch.empty(1, dtype=torch.float64, device="cuda")
+        F = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        first = lambda: m.compute(d, inp["Z"], inp["box"], out=(E, F, None))
+        call = lambda: m.compute(d, None, inp["box"], out=(E, F, None))
+    first()
     torch.cuda.synchronize()
     st = m.status()
     if st != 0:
         raise RuntimeError(f"device status {st} after the first call")
+    E_first = E.detach().cpu().numpy().astype(float)
+    F_first = F.detach().cpu().numpy()
+    tuned = m.autotune(5) if autotune else None
     for _ in range(warmup):
         call()
-    torch.cuda.synchronize()
-    P.nnp_profile_enable(m.h, steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         call()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if m.status() != 0:
+        raise RuntimeError("device status flagged an error during the timed steps")
+    # per-stage event timing (stage launches issued directly; same kernels)
+    P.nnp_profile_enable(m.h, steps)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
     stage_ms, calls = P.nnp_profile_read(m.h)
     P.nnp_profile_enable(m.h, 0)
     cnt = m.read(P._lib.NNP_BUF_NBR_COUNT)
     out = {
         "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "profiled_ms_per_step": (tp1 - tp0) * 1e3 / steps,
         "stage_ms": {k: v / max(calls, 1) for k, v in stage_ms.items()},
-        "E": E.detach().cpu().numpy().astype(float),
-        "F": F.detach().cpu().numpy(),
+        "E": E_first,
+        "F": F_first,
         "rad_pairs": int(cnt[:, 0].sum()),
         "triplets": int((cnt[:, 1].astype(np.int64) * (cnt[:, 1] - 1) // 2).sum()),
         "n": n,
+        "tuned": tuned,
     }
     m.close()
     return out
@@ -162,11 +186,16 @@ def cpu_baseline(cfg, w, inp, reps):
         sample = f"atomic energies of 8,192 random atoms of the {n}-atom box and their gradients, median of {reps}"
         atoms = cs.size
         fn = lambda: orc.evaluate(inp["pos"], inp["Z"], cfg, w, box=inp["box"], centres=cs)
-    times = []
-    for _ in range(reps):
+    # about 10 s of CPU work: at least `reps` evaluations, more when one is short
+    t = time.perf_counter()
+    fn()
+    times = [time.perf_counter() - t]
+    total = max(reps, min(30, math.ceil(10.0 / max(times[0], 1e-3))))
+    for _ in range(total - 1):
         t = time.perf_counter()
         fn()
         times.append(time.perf_counter() - t)
+    sample = sample.replace(f"median of {reps}", f"median of {len(times)}")
     t = statistics.median(times)
     return {"value": atoms / t, "unit": "atom-steps/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": sample, "seconds_per_eval": t}
@@ -213,6 +242,7 @@ def main(argv=None):
     ap.add_argument("--form", default="fp32", choices=["fp32", "bf16"], help="form reported as `value`")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no RMSE, no cpu_baseline)")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in kernel variant choices")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -251,7 +281,7 @@ def main(argv=None):
     forms = {}
     for prec in ("fp32", "bf16"):
         log(f"[bench] timing {prec}: {args.warmup} warmup + {args.steps} steps")
-        forms[prec] = run_form(P, cfg, flat, inp, prec, args.steps, args.warmup)
+        forms[prec] = run_form(P, cfg, flat, inp, prec, args.steps, args.warmup, not args.no_autotune)
         log(f"[bench] {prec}: {forms[prec]['ms_per_step']:.4f} ms/step, "
             f"{n / forms[prec]['ms_per_step'] * 1e3:.4e} atom-steps/s")
 
@@ -265,7 +295,8 @@ def main(argv=None):
         ref = oracle_reference(cfg, w, inp, sample)
     for prec, r in forms.items():
         entry = {"atom_steps_per_s": n / r["ms_per_step"] * 1e3, "ms_per_step": r["ms_per_step"],
-                 "stage_ms": r["stage_ms"]}
+                 "profiled_ms_per_step": r["profiled_ms_per_step"], "stage_ms": r["stage_ms"],
+                 "tuned_variants": r["tuned"]}
         if ref is not None:
             a = ref["atoms"]
             dF = r["F"][a] - ref["F"][a]

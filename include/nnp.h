@@ -128,7 +128,7 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
  * Allocate the workspace for up to max_atoms atoms (all atoms of a call,
  * NNP or not), max_systems systems in one batched call, max_mm MM charges,
  * and per-atom neighbour-list capacities max_rad_nbr (within rc_rad) and
- * max_ang_nbr (within rc_ang); 0 selects the defaults 128 and 48.  May be
+ * max_ang_nbr (within rc_ang); 0 selects the defaults 128 and 64.  May be
  * called again to grow or shrink; synchronises the device.  All device
  * allocation of the model happens here and in nnp_create.
  */
@@ -209,6 +209,32 @@ typedef enum {
  */
 nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_t capacity_bytes,
                            int64_t* elems, int32_t* row_stride, hipStream_t stream);
+
+/*
+ * Autotuner.  Several stages have more than one kernel variant (network:
+ * register-resident wavefronts or row-split workgroups of 16 or 32 atoms;
+ * neighbour search: one wavefront per atom or per cell).  nnp_autotune times
+ * each candidate `reps` times on the workspace of the previous compute call
+ * (same size and geometry) and keeps the fastest for that size bucket
+ * (quarter octaves of the atom count); later calls of that size use it.
+ * chosen (host, [3] or NULL) receives the variants now used for the
+ * neighbour, descriptor and network stages (-1: built-in default).
+ * Synchronises the stream; drops the cached graph.  If the environment
+ * variable NNP_TUNE_CACHE names a file, results are appended to it and
+ * read back by nnp_create for the same GPU architecture and model shape.
+ */
+nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t stream);
+
+/*
+ * HIP-graph replay (enabled by default).  The first call of a configuration
+ * (same output/input pointers, sizes, flags and box) is captured into a HIP
+ * graph; later identical calls replay it with one launch.  Device memory
+ * contents (positions, topology arrays) may change between replays.  Calls
+ * made while the stream is already capturing, or while stage timing is on,
+ * launch their kernels directly.  enable = 0 turns replay off and frees the
+ * cached graph.
+ */
+nnp_status nnp_set_graph(nnp_model* m, int32_t enable);
 
 /*
  * Per-stage timing with HIP events recorded on the call's stream around each

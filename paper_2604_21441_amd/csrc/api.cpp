@@ -1,6 +1,8 @@
 // C ABI entry points: model lifecycle, argument validation, the topology
 // cache, and the per-call sequence of stage launches on the caller's stream.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -19,6 +21,16 @@ nnp_status set_error(nnp_status s, const std::string& msg) {
 
 nnp_status hip_error(hipError_t e, const char* what) {
   return set_error(NNP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int size_bucket(int n) {
+  // quarter-octave buckets of the atom count
+  return n <= 1 ? 0 : (int)std::lround(4.0 * std::log2((double)n));
+}
+
+int tuned_choice(const nnp_model& m, int stage, int n) {
+  auto it = m.tuned.find({stage, size_bucket(n)});
+  return it == m.tuned.end() ? -1 : it->second;
 }
 
 namespace {
@@ -42,6 +54,68 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+void drop_graph(nnp_model* m) {
+  if (m->graph_exec) (void)hipGraphExecDestroy(m->graph_exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->graph_exec = nullptr;
+  m->graph = nullptr;
+  m->graph_key.clear();
+}
+
+// Byte image of everything a captured sequence depends on besides device
+// memory contents: pointers, sizes, flags and the geometry passed by value.
+template <typename... T>
+std::vector<uint8_t> make_key(const T&... parts) {
+  std::vector<uint8_t> k;
+  auto add = [&](const auto& v) {
+    const uint8_t* b = reinterpret_cast<const uint8_t*>(&v);
+    k.insert(k.end(), b, b + sizeof(v));
+  };
+  (add(parts), ...);
+  return k;
+}
+
+// Run `launch` directly, or replay / capture it as a HIP graph.  Identical
+// calls (same key) replay one graph: a single launch instead of ~15.
+// Run `launch(stream)` directly, or replay / capture it as a HIP graph.
+// Identical calls (same key) replay one graph: one launch instead of ~15.
+// Capture happens on the model's own stream (the caller's may be the legacy
+// default stream, which cannot be captured); the graph runs on the caller's.
+template <typename F>
+nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F launch) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (!m->graph_enabled || !m->cap_stream || m->prof_calls < m->prof_max_calls ||
+      (st != nullptr && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone))) {
+    return launch(st);
+  }
+  if (m->graph_exec && key == m->graph_key) {
+    HIP_TRY(hipGraphLaunch(m->graph_exec, st), "graph replay");
+    ++m->graph_replays;
+    return NNP_OK;
+  }
+  drop_graph(m);
+  HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
+  nnp_status s = launch(m->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+  if (s != NNP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return hip_error(e, "graph capture");
+  e = hipGraphInstantiate(&m->graph_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    m->graph_exec = nullptr;
+    return hip_error(e, "graph instantiate");
+  }
+  m->graph = g;
+  m->graph_key = std::move(key);
+  m->graph_replays = 0;
+  HIP_TRY(hipGraphLaunch(m->graph_exec, st), "graph launch");
+  return NNP_OK;
+}
+
 void free_workspace(nnp_model* m) {
   dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_key); dfree(m->d_bin_count);
   dfree(m->d_bin_start); dfree(m->d_cursor); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
@@ -52,6 +126,7 @@ void free_workspace(nnp_model* m) {
   m->h_stage = nullptr;
   m->reserved = false;
   m->topo_mode = -1;
+  drop_graph(m);
 }
 
 int descriptor_length(int S) { return kRadShifts * S + kAngShifts * kAngSects * (S * (S + 1) / 2); }
@@ -72,6 +147,42 @@ nnp_status species_of(const nnp_model* m, int z, int* out) {
       return NNP_OK;
     }
   return set_error(NNP_ESPECIES, "atomic number " + std::to_string(z) + " is not in the species table");
+}
+
+// Tuning cache file (NNP_TUNE_CACHE): one line per entry,
+// "<arch> <network kind> <precision> <stage> <size bucket> <variant>".
+std::string device_arch(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void load_tuning(nnp_model* m) {
+  const char* path = std::getenv("NNP_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string arch = device_arch(m->device);
+  char a[64];
+  int kind, prec, stage, bucket, variant;
+  while (std::fscanf(f, "%63s %d %d %d %d %d", a, &kind, &prec, &stage, &bucket, &variant) == 6)
+    if (arch == a && kind == m->net_kind && prec == (int)m->prec && stage >= 0 && stage < kTuneStages)
+      m->tuned[{stage, bucket}] = variant;
+  std::fclose(f);
+}
+
+void save_tuning(const nnp_model* m) {
+  const char* path = std::getenv("NNP_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  const std::string arch = device_arch(m->device);
+  for (const auto& kv : m->tuned)
+    std::fprintf(f, "%s %d %d %d %d %d\n", arch.c_str(), m->net_kind, (int)m->prec, kv.first.first, kv.first.second,
+                 kv.second);
+  std::fclose(f);
 }
 
 }  // namespace
@@ -198,11 +309,13 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
   if (e == hipSuccess) e = dalloc(&m->d_wvec, vec.size());
   if (e == hipSuccess) e = hipMemcpy(m->d_wvec, vec.data(), vec.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = dalloc(&m->d_status, 1);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMemset(m->d_status, 0, sizeof(int));
   if (e != hipSuccess) {
     nnp_destroy(m);
     return hip_error(e, "nnp_create");
   }
+  load_tuning(m);
   *out = m;
   return NNP_OK;
 }
@@ -220,7 +333,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   m->max_sys = max_systems;
   m->max_mm = max_mm;
   m->max_rad = max_rad_nbr ? max_rad_nbr : 128;
-  m->max_ang = max_ang_nbr ? max_ang_nbr : 48;
+  m->max_ang = max_ang_nbr ? max_ang_nbr : 64;
   int cells_cap = max_atoms > 64 ? max_atoms : 64;
   int per_species_bins = cells_cap > max_systems ? cells_cap : max_systems;
   m->max_bins = m->S * per_species_bins;
@@ -251,6 +364,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_g, n * m->stride));
   chk(dalloc(&m->d_e, n));
   chk(dalloc(&m->d_phi, n));
+  if (e == hipSuccess) e = hipMemset(m->d_bin_count, 0, (size_t)m->max_bins * sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->d_x, 0, n * m->stride * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_g, 0, n * m->stride * sizeof(float));
   if (e == hipSuccess) {
@@ -412,13 +526,20 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
     m->geo.n_bins = 1;
     m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
   }
-  hipError_t e;
-  if (!accumulate) {
-    if ((e = launch_fill_f64(forces, 3 * (int64_t)n_atoms, stream)) != hipSuccess) return hip_error(e, "fill");
-    if (mm_forces && (e = launch_fill_f64(mm_forces, 3 * (int64_t)n_mm, stream)) != hipSuccess)
-      return hip_error(e, "fill");
-  }
-  return run_path(m, n_nnp, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, stream);
+  m->last_n = n_nnp;
+  auto launch = [=](hipStream_t s) -> nnp_status {
+    hipError_t e;
+    if (!accumulate) {
+      if ((e = launch_fill_f64(forces, 3 * (int64_t)n_atoms, s)) != hipSuccess) return hip_error(e, "fill");
+      if (mm_forces && (e = launch_fill_f64(mm_forces, 3 * (int64_t)n_mm, s)) != hipSuccess)
+        return hip_error(e, "fill");
+    }
+    return run_path(m, n_nnp, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, s);
+  };
+  const int mode = 0;
+  return dispatch(m, make_key(mode, pos, energy, forces, mm_forces, mm_pos, mm_q, n_atoms, n_nnp, n_mm, accumulate,
+                              m->geo),
+                  stream, launch);
 }
 
 nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host, const float* pos,
@@ -467,9 +588,14 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
   m->geo.n_bins = n_sys;
   m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
   if (m->S * n_sys > m->max_bins) return set_error(NNP_ECAPACITY, "too many systems for the reserved bins");
-  hipError_t e;
-  if ((e = launch_fill_f64(forces, 3 * (int64_t)n, stream)) != hipSuccess) return hip_error(e, "fill");
-  return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, stream);
+  m->last_n = n;
+  auto launch = [=](hipStream_t s) -> nnp_status {
+    hipError_t e;
+    if ((e = launch_fill_f64(forces, 3 * (int64_t)n, s)) != hipSuccess) return hip_error(e, "fill");
+    return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, s);
+  };
+  const int mode = 1;
+  return dispatch(m, make_key(mode, pos, energies, forces, n, n_sys, m->geo), stream, launch);
 }
 
 nnp_status nnp_get_status(nnp_model* m, hipStream_t stream) {
@@ -539,8 +665,67 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
   return NNP_OK;
 }
 
+nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t stream) {
+  if (!m || reps < 1) return set_error(NNP_EINVAL, "bad argument");
+  if (!m->reserved || m->last_n <= 0) return set_error(NNP_ESTATE, "nnp_autotune needs a previous compute call");
+  HIP_TRY(hipStreamSynchronize(stream), "nnp_autotune");
+  drop_graph(m);
+  const int n = m->last_n;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "nnp_autotune");
+  HIP_TRY(hipEventCreate(&e1), "nnp_autotune");
+  auto time_stage = [&](int stage, int v, float* ms) -> nnp_status {
+    m->force_variant[stage] = v;
+    hipError_t e = hipSuccess;
+    auto run = [&]() {
+      return stage == kTuneNetwork ? launch_mlp(*m, n, stream) : launch_neighbours(*m, n, stream);
+    };
+    e = run();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    m->force_variant[stage] = -1;
+    return e == hipSuccess ? NNP_OK : hip_error(e, "nnp_autotune");
+  };
+  const int stages[2] = {kTuneNetwork, kTuneNeighbours};
+  nnp_status status = NNP_OK;
+  for (int st : stages) {
+    int nv = st == kTuneNetwork ? 3 : (m->geo.n_bins >= 2 ? 2 : 1);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int v = 0; v < nv && status == NNP_OK; ++v) {
+      float ms = 0.f;
+      status = time_stage(st, v, &ms);
+      if (status == NNP_OK && (v == 0 || ms < best_ms)) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    if (status != NNP_OK) break;
+    m->tuned[{st, size_bucket(n)}] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != NNP_OK) return status;
+  if (chosen) {
+    for (int st = 0; st < kTuneStages; ++st) chosen[st] = tuned_choice(*m, st, n);
+  }
+  save_tuning(m);
+  return NNP_OK;
+}
+
+nnp_status nnp_set_graph(nnp_model* m, int32_t enable) {
+  if (!m) return set_error(NNP_EINVAL, "null model");
+  m->graph_enabled = enable != 0;
+  if (!m->graph_enabled) drop_graph(m);
+  return NNP_OK;
+}
+
 nnp_status nnp_profile_enable(nnp_model* m, int32_t max_calls) {
   if (!m || max_calls < 0) return set_error(NNP_EINVAL, "bad argument");
+  HIP_TRY(hipDeviceSynchronize(), "nnp_profile_enable");
   for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);
   m->prof_ev.clear();
   m->prof_calls = 0;
@@ -573,6 +758,9 @@ nnp_status nnp_profile_read(nnp_model* m, double* ms_total, int64_t* calls, hipS
 
 void nnp_destroy(nnp_model* m) {
   if (!m) return;
+  drop_graph(m);
+  if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+  m->cap_stream = nullptr;
   for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);
   m->prof_ev.clear();
   (void)hipDeviceSynchronize();

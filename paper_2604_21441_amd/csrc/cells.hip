@@ -63,9 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
 }
 
 // Exclusive scan of the bin histogram by one workgroup; also seeds the
-// scatter cursors.
+// scatter cursors and clears the histogram for the next call (it is zeroed
+// once when the workspace is reserved).
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ count,
+__global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ count,
                                                        int* __restrict__ start,
                                                        int* __restrict__ cursor, int n) {
   __shared__ int part[kScanThreads];
@@ -86,9 +87,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ c
   }
   int run = tid == 0 ? 0 : part[tid - 1];
   for (int i = lo; i < hi; ++i) {
+    const int c = count[i];
     start[i] = run;
     cursor[i] = run;
-    run += count[i];
+    run += c;
+    count[i] = 0;   // the histogram starts from zero in the next call
   }
   if (tid == kScanThreads - 1) start[n] = part[kScanThreads - 1];
 }
@@ -283,6 +286,161 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   }
 }
 
+// Same lists as k_neighbours, one wavefront per bin (periodic cell, or one
+// system of a batch): the bin's centre atoms (all species, up to 64 at a
+// time) are staged in LDS, and the stencil's candidates, one per lane and in
+// ascending slot order, are tested against every centre in turn, each
+// centre's accepted candidates being compacted with a ballot.  The stencil is
+// set up once per bin instead of once per atom.  Per-centre list lengths live
+// in the register of the lane with the centre's index.
+__global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g) {
+#pragma clang fp contract(off)
+  __shared__ int s_cell[kMaxStencil];
+  __shared__ int s_start[kMaxStencil];
+  __shared__ int s_off[kMaxStencil];
+  __shared__ float4 s_cpos[64];
+  __shared__ int s_cid[64];
+  const int cell = blockIdx.x;
+  const int lane = threadIdx.x;
+  int nst = 1;
+  int my_cell = -1;
+  if (g.periodic) {
+    int c[3], nd[3];
+    c[0] = cell / (g.nc[1] * g.nc[2]);
+    c[1] = (cell / g.nc[2]) % g.nc[1];
+    c[2] = cell % g.nc[2];
+    for (int k = 0; k < 3; ++k) nd[k] = g.nc[k] >= 3 ? 3 : g.nc[k];
+    nst = nd[0] * nd[1] * nd[2];
+    if (lane < nst) {
+      int o[3] = {lane / (nd[1] * nd[2]), (lane / nd[2]) % nd[1], lane % nd[2]};
+      int w[3];
+      for (int k = 0; k < 3; ++k) {
+        int off = nd[k] == 3 ? o[k] - 1 : o[k];
+        int x = c[k] + off;
+        w[k] = x < 0 ? x + g.nc[k] : (x >= g.nc[k] ? x - g.nc[k] : x);
+      }
+      my_cell = (w[0] * g.nc[1] + w[1]) * g.nc[2] + w[2];
+    }
+  } else if (lane == 0) {
+    my_cell = cell;
+  }
+  int rank = 0;
+  for (int l = 0; l < nst; ++l) {
+    int o = __shfl(my_cell, l, 64);
+    rank += (o < my_cell) ? 1 : 0;
+  }
+  if (lane < nst) s_cell[rank] = my_cell;
+
+  // centre atoms of this bin: species-major ranges of slots
+  int c_lo[kMaxSpecies], c_n[kMaxSpecies];
+  int n_centres = 0;
+  for (int s = 0; s < a.S; ++s) {
+    c_lo[s] = a.bin_start[s * g.n_bins + cell];
+    c_n[s] = a.bin_start[s * g.n_bins + cell + 1] - c_lo[s];
+    n_centres += c_n[s];
+  }
+  const uint64_t lt = __lanemask_lt();
+  for (int cb = 0; cb < n_centres; cb += 64) {
+    const int nc = min(64, n_centres - cb);
+    int my_i = -1;
+    if (lane < nc) {
+      int q = cb + lane, s = 0;
+      while (q >= c_n[s]) { q -= c_n[s]; ++s; }
+      my_i = c_lo[s] + q;
+      s_cid[lane] = my_i;
+      s_cpos[lane] = a.spos[my_i];
+    }
+    int nr = 0, na = 0;   // lists of centre `lane`
+    bool overflow = false;
+    __syncthreads();
+    for (int s = 0; s < a.S; ++s) {
+      if (lane < nc) {
+        a.rad_off[(int64_t)my_i * (a.S + 1) + s] = nr;
+        a.ang_off[(int64_t)my_i * (a.S + 1) + s] = na;
+      }
+      int st = 0, cnt = 0;
+      if (lane < nst) {
+        int b = s * g.n_bins + s_cell[lane];
+        st = a.bin_start[b];
+        cnt = a.bin_start[b + 1] - st;
+      }
+      int inc = cnt;
+      for (int off = 1; off < 32; off <<= 1) {
+        int v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+      }
+      const int total = __shfl(inc, nst - 1, 64);
+      if (lane < nst) {
+        s_start[lane] = st;
+        s_off[lane] = inc - cnt;
+      }
+      __syncthreads();
+      for (int c0 = 0; c0 < total; c0 += 64) {
+        const int c = c0 + lane;
+        int j = -1;
+        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c < total) {
+          int lo = 0, hi = nst - 1;
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
+          }
+          j = s_start[lo] + (c - s_off[lo]);
+          pj = a.spos[j];
+        }
+        for (int ci = 0; ci < nc; ++ci) {
+          const float4 pi = s_cpos[ci];
+          const int i = s_cid[ci];
+          bool in_r = false, in_a = false;
+          if (j >= 0 && j != i) {
+            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            if (g.periodic) {
+              float sx = rintf(dx * g.inv_box[0]);
+              float sy = rintf(dy * g.inv_box[1]);
+              float sz = rintf(dz * g.inv_box[2]);
+              float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+              dx = dx - tx; dy = dy - ty; dz = dz - tz;
+            }
+            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+            float r2 = xx + yy;
+            r2 = r2 + zz;
+            in_r = r2 < a.rc2;
+            in_a = r2 < a.rca2;
+          }
+          const int base_r = __builtin_amdgcn_readlane(nr, ci);
+          const int base_a = __builtin_amdgcn_readlane(na, ci);
+          const uint64_t mr = __ballot(in_r);
+          const int pr = base_r + __popcll(mr & lt);
+          const bool in_a2 = in_a && pr < a.max_rad;
+          const uint64_t ma = __ballot(in_a2);
+          const int pa = base_a + __popcll(ma & lt);
+          if (in_r && pr < a.max_rad) a.rad[(int64_t)i * a.max_rad + pr] = j;
+          if (in_a2 && pa < a.max_ang) {
+            a.ang[(int64_t)i * a.max_ang + pa] = j;
+            a.angpos[(int64_t)i * a.max_ang + pa] = pr;
+          }
+          if (lane == ci) {
+            nr += __popcll(mr);
+            na += __popcll(ma);
+            if (nr > a.max_rad || na > a.max_ang) {
+              overflow = true;
+              nr = min(nr, a.max_rad);
+              na = min(na, a.max_ang);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (lane < nc) {
+      a.rad_off[(int64_t)my_i * (a.S + 1) + a.S] = nr;
+      a.ang_off[(int64_t)my_i * (a.S + 1) + a.S] = na;
+      if (overflow) atomicOr(a.status, kStatusCapacity);
+    }
+    __syncthreads();
+  }
+}
+
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -290,10 +448,6 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   const Geometry& g = m.geo;
   int nb = m.S * g.n_bins;
-  if (nb > 0) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nb, kBlock)), dim3(kBlock), 0, st,
-                       m.d_bin_count, nb, 0);
-  }
   if (n > 0) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
                        m.d_sigma, m.d_sys, g, m.d_key, m.d_bin_count, m.d_status);
@@ -330,7 +484,18 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   a.max_rad = m.max_rad;
   a.max_ang = m.max_ang;
   a.status = m.d_status;
-  hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);
+  // One wavefront per bin amortises the stencil set-up but needs enough bins
+  // to fill the chip; with few bins (small boxes, one open system) work per
+  // atom.  The autotuner may choose otherwise.
+  int v = m.force_variant[kTuneNeighbours] >= 0 ? m.force_variant[kTuneNeighbours]
+                                                 : tuned_choice(m, kTuneNeighbours, n);
+  if (v < 0) v = m.geo.n_bins >= 2048 ? 1 : 0;
+  if (m.geo.n_bins < 2) v = 0;
+  if (v == 1) {
+    hipLaunchKernelGGL(k_neighbours_cell, dim3(m.geo.n_bins), dim3(64), 0, st, a, m.geo);
+  } else {
+    hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);
+  }
   return hipGetLastError();
 }
 

@@ -91,8 +91,309 @@ __device__ __forceinline__ float celu_grad_from_h(float h, float inv_alpha) {
 //   F1 [N1 x K0], F2 [N2 x N1], F3 [N3 x N2]   forward,  A = W_l
 //   B1 [K0 x N1], B2 [N1 x N2], B3 [N2 x N3]   backward, A = W_l^T
 // and of the vectors (FP32): b1[N1] b2[N2] b3[N3] w4[N3] b4[4].
+//
+// One workgroup (4 wavefronts) owns a tile of 16*C atoms of one species.
+// Every product is split by output row tiles: wavefront w computes the row
+// tiles r = w, w+4, ... for all C column tiles (each weight fragment it loads
+// serves C matrix-core steps) and publishes them in LDS, in the same fragment
+// layout, for the next product.  Each wavefront keeps its own post-activation
+// tiles in registers for the CELU derivative of the backward pass.
+constexpr int kWaves = 4;
+
+template <int R>
+struct Own {  // number of row tiles r = w + 4 j owned by one wavefront
+  static constexpr int n = (R + kWaves - 1) / kWaves;
+};
+
+// out[j][c] = A-rows (w + 4 j) of W [R x K] times the K/16 LDS tiles `in[c][kb]`.
+template <int R, int K, bool BF16, int C>
+__device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* in, int in_tiles, v4f (*out)[C],
+                                         int w, int lane) {
+  constexpr int NJ = Own<R>::n;
+  if constexpr (!BF16) {
+    constexpr int KB = K / 16;
+    const v4f* Wp = reinterpret_cast<const v4f*>(W);
+#pragma unroll 2
+    for (int kb = 0; kb < KB; ++kb) {
+      v4f bv[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) bv[c] = in[(c * in_tiles + kb) * 64 + lane];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int r = w + kWaves * j;
+        if (r < R) {
+          const v4f wv = Wp[(r * KB + kb) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < C; ++c) out[j][c] = mfma_step(wv, bv[c], out[j][c]);
+        }
+      }
+    }
+  } else {
+    constexpr int KB = K / 32;
+    const v8bf* Wp = reinterpret_cast<const v8bf*>(W);
+#pragma unroll 2
+    for (int kb = 0; kb < KB; ++kb) {
+      v8bf bv[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        bv[c] = to_bf16x8(in[(c * in_tiles + 2 * kb) * 64 + lane], in[(c * in_tiles + 2 * kb + 1) * 64 + lane]);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int r = w + kWaves * j;
+        if (r < R) {
+          const v8bf wv = Wp[(r * KB + kb) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            out[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, bv[c], out[j][c], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+template <int K0, int N1, int N2, int N3, bool BF16, int C>
+__global__ __launch_bounds__(256) void k_mlp_split(MlpArgs a, float alpha) {
+  constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
+  constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
+  constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
+  constexpr int TX = (K0 > N2 ? K0 : N2) / 16;        // tiles of buffer X (x, then H2, then delta2)
+  constexpr int TA = (N1 > N3 ? N1 : N3) / 16;        // tiles of buffer A (H1, then delta3, then delta1)
+  using Elem = typename std::conditional<BF16, __bf16, float>::type;
+  __shared__ v4f bufX[C * TX * 64];
+  __shared__ v4f bufA[C * TA * 64];
+  __shared__ float epart[kWaves][C * 16];
+
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4;
+  const int col = lane & 15;
+
+  // workgroup -> (species, tile of 16*C rows)
+  int s = -1, row0 = 0, row_end = 0, before = 0;
+  for (int ss = 0; ss < a.S; ++ss) {
+    int b0 = a.bin_start[ss * a.n_bins], b1 = a.bin_start[(ss + 1) * a.n_bins];
+    int nt = (b1 - b0 + 16 * C - 1) / (16 * C);
+    if ((int)blockIdx.x < before + nt) {
+      s = ss;
+      row0 = b0 + ((int)blockIdx.x - before) * 16 * C;
+      row_end = b1;
+      break;
+    }
+    before += nt;
+  }
+  if (s < 0) return;   // whole workgroup exits together
+  const float inv_alpha = 1.f / alpha;
+  const float inv_alpha_l2 = kLog2e / alpha;
+
+  // stage x in fragment layout: tile (c, kb), lane l holds x[row c*16 + l%16][16 kb + 4 (l/16) .. +3]
+  for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
+    const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
+    const int row = row0 + c * 16 + (l & 15);
+    v4f v = v4f{0.f, 0.f, 0.f, 0.f};
+    if (row < row_end) v = *reinterpret_cast<const v4f*>(a.x + (int64_t)row * a.stride + 16 * kb + 4 * (l >> 4));
+    bufX[(c * TX + kb) * 64 + l] = v;
+  }
+  float e_acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) e_acc[c] = 0.f;
+  __syncthreads();
+
+  for (int mem = 0; mem < a.n_members; ++mem) {
+    const Elem* Wm = reinterpret_cast<const Elem*>(a.wmat) + (int64_t)(mem * a.S + s) * a.mat_per_species;
+    const float* V = a.wvec + (int64_t)(mem * a.S + s) * a.vec_per_species;
+
+    // ---- layer 1: h1 = celu(W1 x + b1)       X -> A
+    v4f h1[Own<N1>::n][C];
+#pragma unroll
+    for (int j = 0; j < Own<N1>::n; ++j) {
+      const int r = w + kWaves * j;
+      const v4f bias = r < N1 / 16 ? *reinterpret_cast<const v4f*>(V + ob1 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < C; ++c) h1[j][c] = bias;
+    }
+    gemm_lds<N1 / 16, K0, BF16, C>(Wm + oF1, bufX, TX, h1, w, lane);
+#pragma unroll
+    for (int j = 0; j < Own<N1>::n; ++j) {
+      const int r = w + kWaves * j;
+      if (r < N1 / 16) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) h1[j][c][t] = celu_f(h1[j][c][t], alpha, inv_alpha_l2);
+          bufA[(c * TA + r) * 64 + lane] = h1[j][c];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- layer 2: h2 = celu(W2 h1 + b2)      A -> X
+    v4f h2[Own<N2>::n][C];
+#pragma unroll
+    for (int j = 0; j < Own<N2>::n; ++j) {
+      const int r = w + kWaves * j;
+      const v4f bias = r < N2 / 16 ? *reinterpret_cast<const v4f*>(V + ob2 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < C; ++c) h2[j][c] = bias;
+    }
+    gemm_lds<N2 / 16, N1, BF16, C>(Wm + oF2, bufA, TA, h2, w, lane);
+    __syncthreads();   // everyone has read A (h1) and X (x) before X is overwritten
+#pragma unroll
+    for (int j = 0; j < Own<N2>::n; ++j) {
+      const int r = w + kWaves * j;
+      if (r < N2 / 16) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) h2[j][c][t] = celu_f(h2[j][c][t], alpha, inv_alpha_l2);
+          bufX[(c * TX + r) * 64 + lane] = h2[j][c];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- layer 3 and the output layer; delta3 = w4 o celu'(h3)   X -> A
+    v4f h3[Own<N3>::n][C];
+#pragma unroll
+    for (int j = 0; j < Own<N3>::n; ++j) {
+      const int r = w + kWaves * j;
+      const v4f bias = r < N3 / 16 ? *reinterpret_cast<const v4f*>(V + ob3 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < C; ++c) h3[j][c] = bias;
+    }
+    gemm_lds<N3 / 16, N2, BF16, C>(Wm + oF3, bufX, TX, h3, w, lane);
+    float ep[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ep[c] = 0.f;
+#pragma unroll
+    for (int j = 0; j < Own<N3>::n; ++j) {
+      const int r = w + kWaves * j;
+      if (r < N3 / 16) {
+        const v4f w4 = *reinterpret_cast<const v4f*>(V + ow4 + 16 * r + 4 * q);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          v4f d;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float h = celu_f(h3[j][c][t], alpha, inv_alpha_l2);
+            ep[c] += w4[t] * h;
+            d[t] = w4[t] * celu_grad_from_h(h, inv_alpha);
+          }
+          bufA[(c * TA + r) * 64 + lane] = d;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      float v = ep[c];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (q == 0) epart[w][c * 16 + col] = v;
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        e_acc[c] += epart[0][c * 16 + col] + epart[1][c * 16 + col] + epart[2][c * 16 + col] +
+                    epart[3][c * 16 + col] + V[ob4];
+    }
+
+    // ---- delta2 = (W3^T delta3) o celu'(h2)    A -> X
+    v4f d2[Own<N2>::n][C];
+#pragma unroll
+    for (int j = 0; j < Own<N2>::n; ++j)
+#pragma unroll
+      for (int c = 0; c < C; ++c) d2[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    gemm_lds<N2 / 16, N3, BF16, C>(Wm + oB3, bufA, TA, d2, w, lane);
+#pragma unroll
+    for (int j = 0; j < Own<N2>::n; ++j) {
+      const int r = w + kWaves * j;
+      if (r < N2 / 16) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) d2[j][c][t] *= celu_grad_from_h(h2[j][c][t], inv_alpha);
+          bufX[(c * TX + r) * 64 + lane] = d2[j][c];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- delta1 = (W2^T delta2) o celu'(h1)    X -> A
+    v4f d1[Own<N1>::n][C];
+#pragma unroll
+    for (int j = 0; j < Own<N1>::n; ++j)
+#pragma unroll
+      for (int c = 0; c < C; ++c) d1[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
+    gemm_lds<N1 / 16, N2, BF16, C>(Wm + oB2, bufX, TX, d1, w, lane);
+#pragma unroll
+    for (int j = 0; j < Own<N1>::n; ++j) {
+      const int r = w + kWaves * j;
+      if (r < N1 / 16) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) d1[j][c][t] *= celu_grad_from_h(h1[j][c][t], inv_alpha);
+          bufA[(c * TA + r) * 64 + lane] = d1[j][c];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- dE/dx = W1^T delta1 (row tiles over the input features), to memory
+    {
+      v4f gx[Own<K0 / 16>::n][C];
+#pragma unroll
+      for (int j = 0; j < Own<K0 / 16>::n; ++j)
+#pragma unroll
+        for (int c = 0; c < C; ++c) gx[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
+      gemm_lds<K0 / 16, N1, BF16, C>(Wm + oB1, bufA, TA, gx, w, lane);
+#pragma unroll
+      for (int j = 0; j < Own<K0 / 16>::n; ++j) {
+        const int r = w + kWaves * j;
+        if (r < K0 / 16) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int row = row0 + c * 16 + col;
+            if (row < row_end) {
+              v4f* dst = reinterpret_cast<v4f*>(a.g + (int64_t)row * a.stride + 16 * r + 4 * q);
+              v4f v = gx[j][c];
+              if (a.n_members > 1) {
+                if (mem > 0) v += *dst;
+                if (mem == a.n_members - 1) v *= (1.f / (float)a.n_members);
+              }
+              *dst = v;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();   // buffers are reused by the next ensemble member
+  }
+  // atomic energies and the tile's FP64 partial sum
+  if (w == 0) {
+    double ev = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int row = row0 + c * 16 + col;
+      const float e_atom = e_acc[c] / (float)a.n_members;
+      if (row < row_end && q == 0) {
+        a.e[row] = e_atom;
+        ev += (double)e_atom;
+      }
+    }
+    if (a.part != nullptr) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) ev += __shfl_xor(ev, off, 64);
+      if (lane == 0) a.part[blockIdx.x] = ev;
+    }
+  }
+}
+
+// Register-resident variant: each wavefront owns 16 atoms and keeps the whole
+// chain (activations and deltas) in registers; no LDS, no barriers.  Cheapest
+// when the products are short (BF16 operands).
 template <int K0, int N1, int N2, int N3, bool BF16>
-__global__ __launch_bounds__(kBlock) void k_mlp(MlpArgs a, float alpha) {
+__global__ __launch_bounds__(kBlock) void k_mlp_reg(MlpArgs a, float alpha) {
   constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
   constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
   constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
@@ -272,11 +573,11 @@ __global__ __launch_bounds__(kBlock) void k_mlp(MlpArgs a, float alpha) {
 constexpr int kFin = 256;
 __global__ __launch_bounds__(kFin) void k_energy_final(const double* __restrict__ part,
                                                        const int* __restrict__ bin_start, int n_bins, int S,
-                                                       double* __restrict__ out, int accumulate,
+                                                       int tile_rows, double* __restrict__ out, int accumulate,
                                                        int* __restrict__ status) {
   __shared__ double red[kFin];
   int tiles = 0;
-  for (int s = 0; s < S; ++s) tiles += (bin_start[(s + 1) * n_bins] - bin_start[s * n_bins] + 15) >> 4;
+  for (int s = 0; s < S; ++s) tiles += (bin_start[(s + 1) * n_bins] - bin_start[s * n_bins] + tile_rows - 1) / tile_rows;
   double acc = 0.0;
   for (int t = threadIdx.x; t < tiles; t += kFin) acc += part[t];
   red[threadIdx.x] = acc;
@@ -323,15 +624,35 @@ __global__ __launch_bounds__(kRed) void k_energy(const float* __restrict__ e, co
 }
 
 template <int K0, int N1, int N2, int N3, bool BF16>
-hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, hipStream_t st) {
-  int64_t tiles = (n + 15) / 16 + m.S;
-  int64_t threads = tiles * 64;
-  hipLaunchKernelGGL((k_mlp<K0, N1, N2, N3, BF16>), dim3((unsigned)((threads + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, st, a, m.celu_alpha);
+hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream_t st) {
+  if (variant == 0) {        // register-resident, one wavefront per 16 atoms
+    const int64_t waves = (n + 15) / 16 + m.S;
+    hipLaunchKernelGGL((k_mlp_reg<K0, N1, N2, N3, BF16>), dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, a, m.celu_alpha);
+  } else if (variant == 2) { // row split, 32 atoms per workgroup
+    const int64_t tiles = (n + 31) / 32 + m.S;
+    hipLaunchKernelGGL((k_mlp_split<K0, N1, N2, N3, BF16, 2>), dim3((unsigned)tiles), dim3(256), 0, st, a,
+                       m.celu_alpha);
+  } else {                   // row split, 16 atoms per workgroup
+    const int64_t tiles = (n + 15) / 16 + m.S;
+    hipLaunchKernelGGL((k_mlp_split<K0, N1, N2, N3, BF16, 1>), dim3((unsigned)tiles), dim3(256), 0, st, a,
+                       m.celu_alpha);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
+
+// Network kernel variant: 0 register-resident (16 atoms per wavefront),
+// 1 / 2 row split over 4 wavefronts with 16 / 32 atoms per workgroup.  A
+// tuned choice for this size wins; otherwise BF16 products are short enough
+// for the register-resident kernel, and FP32 ones need the row split.
+int mlp_variant(const nnp_model& m, int n) {
+  int v = tuned_choice(m, kTuneNetwork, n);
+  if (v >= 0) return v;
+  if (m.prec == NNP_BF16) return 0;
+  return n >= 65536 ? 2 : 1;
+}
 
 hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
@@ -351,13 +672,15 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.status = m.d_status;
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
+  const int v = m.force_variant[kTuneNetwork] >= 0 ? m.force_variant[kTuneNetwork] : mlp_variant(m, n);
+  m.mlp_cols = v == 2 ? 2 : 1;
   switch (m.net_kind) {
     case 0:
-      return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, st);
+      return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, v, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, v, st);
     case 1:
-      return bf ? run_mlp<384, 256, 192, 160, true>(m, a, n, st) : run_mlp<384, 256, 192, 160, false>(m, a, n, st);
+      return bf ? run_mlp<384, 256, 192, 160, true>(m, a, n, v, st) : run_mlp<384, 256, 192, 160, false>(m, a, n, v, st);
     case 2:
-      return bf ? run_mlp<416, 256, 192, 160, true>(m, a, n, st) : run_mlp<416, 256, 192, 160, false>(m, a, n, st);
+      return bf ? run_mlp<416, 256, 192, 160, true>(m, a, n, v, st) : run_mlp<416, 256, 192, 160, false>(m, a, n, v, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -366,7 +689,7 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
 hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st) {
   if (m.geo.periodic || m.geo.n_bins == 1) {
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kFin), 0, st, m.d_part, m.d_bin_start, m.geo.n_bins, m.S,
-                       energies, accumulate, m.d_status);
+                       16 * m.mlp_cols, energies, accumulate, m.d_status);
   } else {
     hipLaunchKernelGGL(k_energy, dim3(n_sys), dim3(kRed), 0, st, m.d_e, m.d_bin_start, m.geo.n_bins, m.S, 0,
                        energies, accumulate, m.d_status);

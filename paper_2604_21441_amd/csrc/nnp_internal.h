@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "nnp.h"
@@ -18,6 +20,9 @@ constexpr int kAngSects = 4;     // angle sections per species pair
 constexpr int kMaxSpecies = 4;
 constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
 constexpr int kTileAtoms = 16;   // atoms per wavefront in the network kernels
+
+// Stages with several kernel variants chosen by the autotuner.
+enum TuneStage { kTuneNeighbours = 0, kTuneDescriptor = 1, kTuneNetwork = 2, kTuneStages = 3 };
 
 // Device status bits.
 constexpr int kStatusCapacity = 1;
@@ -82,6 +87,9 @@ struct nnp_model {
   std::vector<int> widths;              // unpadded widths
   float celu_alpha = 0.1f;
   nnp::DescParams dp{};
+  int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
+  std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
+  int force_variant[nnp::kTuneStages] = {-1, -1, -1};   // set while timing candidates
   int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
   std::vector<float> w_host;            // canonical FP32 weights, draw order
 
@@ -128,6 +136,14 @@ struct nnp_model {
   std::vector<int> topo_Z, topo_idx, topo_offsets;
   int n_nnp = 0;
 
+  // graph replay of identical calls
+  bool graph_enabled = true;
+  hipStream_t cap_stream = nullptr;  // capture stream (default priority)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint8_t> graph_key;
+  int graph_replays = 0;
+
   // stage timing
   std::vector<hipEvent_t> prof_ev;   // [call][stage][2]
   int prof_max_calls = 0, prof_calls = 0;
@@ -138,6 +154,10 @@ struct nnp_model {
 };
 
 namespace nnp {
+
+// autotuner (api.cpp): tuned variant of a stage for n atoms, or -1
+int tuned_choice(const nnp_model& m, int stage, int n);
+int size_bucket(int n);
 
 // error helpers (api.cpp)
 nnp_status set_error(nnp_status s, const std::string& msg);

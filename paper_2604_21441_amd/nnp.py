@@ -18,7 +18,7 @@ from . import _lib as L
 
 __all__ = [
     "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
-    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
 
@@ -162,6 +162,17 @@ def nnp_read_buffer(h, which: int, stream=None) -> np.ndarray:
     return out
 
 
+def nnp_autotune(h, reps: int = 5, stream=None) -> dict:
+    """Time every kernel variant on the last call's workspace and keep the fastest."""
+    chosen = (C.c_int32 * 3)()
+    _check(L.load().nnp_autotune(h, int(reps), chosen, _stream(stream)), "nnp_autotune")
+    return {"neighbours": chosen[0], "descriptor": chosen[1], "network": chosen[2]}
+
+
+def nnp_set_graph(h, enable: bool) -> None:
+    _check(L.load().nnp_set_graph(h, 1 if enable else 0), "nnp_set_graph")
+
+
 def nnp_profile_enable(h, max_calls: int) -> None:
     _check(L.load().nnp_profile_enable(h, int(max_calls)), "nnp_profile_enable")
 
@@ -200,13 +211,19 @@ class NNPModel:
             self.reserve(max(n_atoms, base[0]), max(n_sys, base[1]), max(n_mm, base[2]), base[3], base[4])
 
     def compute(self, pos: torch.Tensor, Z=None, box=None, nnp_idx=None, mm_pos=None, mm_q=None,
-                accumulate_into=None, stream=None):
-        """Energy [1] (float64) and forces [n, 3] (float64) on pos.device; MM forces if MM charges are given."""
+                accumulate_into=None, out=None, stream=None):
+        """Energy [1] (float64) and forces [n, 3] (float64) on pos.device; MM forces if MM charges are given.
+
+        Z=None reuses the topology of the previous call.  ``out=(E, F, F_mm)`` writes into
+        preallocated tensors; ``accumulate_into=(E, F, F_mm)`` adds to them instead.
+        """
         n = pos.shape[0]
         self._ensure(n, 1, 0 if mm_pos is None else mm_pos.shape[0])
         dev = pos.device
         if accumulate_into is not None:
             E, F, Fmm = accumulate_into
+        elif out is not None:
+            E, F, Fmm = out
         else:
             E = torch.empty(1, dtype=torch.float64, device=dev)
             F = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -215,13 +232,23 @@ class NNPModel:
                     accumulate=accumulate_into is not None, stream=stream)
         return E, F, Fmm
 
-    def compute_batch(self, pos: torch.Tensor, Z, offsets, stream=None):
+    def compute_batch(self, pos: torch.Tensor, Z, offsets, out=None, stream=None):
+        """Per-system energies [n_sys] and forces [n, 3] (float64) of packed open systems."""
         offsets = np.asarray(offsets, dtype=np.int32)
         self._ensure(pos.shape[0], offsets.size - 1)
-        E = torch.empty(offsets.size - 1, dtype=torch.float64, device=pos.device)
-        F = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
+        if out is not None:
+            E, F = out
+        else:
+            E = torch.empty(offsets.size - 1, dtype=torch.float64, device=pos.device)
+            F = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
         nnp_compute_batch(self.h, offsets, pos, Z, E, F, stream=stream)
         return E, F
+
+    def set_graph(self, enable: bool) -> None:
+        nnp_set_graph(self.h, enable)
+
+    def autotune(self, reps: int = 5) -> dict:
+        return nnp_autotune(self.h, reps)
 
     def status(self, stream=None) -> int:
         return nnp_get_status(self.h, stream)

@@ -220,6 +220,96 @@ def test_autograd_function(P, water_models, boxes):
     assert torch.allclose(x.grad.double(), -F.double(), rtol=1e-5, atol=1e-6)
 
 
+def test_graph_replay_matches_eager(P, water_models, boxes):
+    """Replays of the captured call equal direct launches, with eager work and syncs between replays."""
+    pos, Z, box = boxes["c2"]
+    m = water_models["fp32"]
+    d = torch.from_numpy(pos).cuda()
+    m.set_graph(False)
+    E0, F0, _ = m.compute(d, Z, box)
+    torch.cuda.synchronize()
+    E0, F0 = E0.clone(), F0.clone()
+    m.set_graph(True)
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    F = torch.empty((len(Z), 3), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        E.fill_(123.0)
+        F.fill_(-7.0)
+        m.compute(d, Z if rep == 0 else None, box, out=(E, F, None))
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert abs(E.item() - E0.item()) < 1e-12 * abs(E0.item()), rep
+        assert torch.allclose(F, F0, rtol=0, atol=1e-12), rep
+    # a moved configuration through the same graph gives the new answer
+    d2 = d + 0.01
+    torch.cuda.synchronize()
+    d.copy_(d2)
+    m.compute(d, None, box, out=(E, F, None))
+    m.set_graph(False)
+    E2, F2, _ = m.compute(d, None, box)
+    torch.cuda.synchronize()
+    assert abs(E.item() - E2.item()) < 1e-12 * abs(E2.item())
+    m.set_graph(True)
+
+
+def test_autotune_keeps_results(P, w_water):
+    """Every kernel variant the autotuner may pick computes the same energy and forces."""
+    pos, Z, box = sy.water_box(4096, 49.7, seed=0)
+    d = torch.from_numpy(pos).cuda()
+    for prec in ("fp32", "bf16"):
+        m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision=prec)
+        E0, F0, _ = m.compute(d, Z, box)
+        torch.cuda.synchronize()
+        E0, F0 = E0.clone(), F0.clone()
+        chosen = m.autotune(3)
+        assert chosen["network"] in (0, 1, 2) and chosen["neighbours"] in (0, 1)
+        E1, F1, _ = m.compute(d, Z, box)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        assert abs(E1.item() - E0.item()) < 1e-9 * abs(E0.item())
+        assert torch.allclose(F1, F0, rtol=0, atol=1e-9)
+        m.close()
+
+
+def test_neighbour_sets_batched_and_open(P, w_hcno):
+    pos, Z, off = sy.walk_batch(6, seed=7)
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
+    m.compute_batch(torch.from_numpy(pos).cuda(), Z, off)
+    torch.cuda.synchronize()
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    sigma = orc.species_index(Z, HCNO["species"])
+    sys_of = np.repeat(np.arange(6), np.diff(off))
+    key = sigma * 6 + sys_of
+    assert np.array_equal(m.read(P._lib.NNP_BUF_KEY), key)
+    assert np.array_equal(perm, np.argsort(key, kind="stable"))
+    cnt = m.read(P._lib.NNP_BUF_NBR_COUNT)
+    lists = m.read(P._lib.NNP_BUF_NBR_RAD)
+    ref = set()
+    for s in range(6):
+        I, J = orc.neighbours_fp32(pos[off[s]:off[s + 1]], HCNO["rc_rad"], None)
+        ref.update(zip((I + off[s]).tolist(), (J + off[s]).tolist()))
+    got = set()
+    for i in range(len(perm)):
+        row = lists[i, :cnt[i, 0]]
+        assert np.all(np.diff(row) > 0) or np.all(np.diff(sigma[perm[row]]) >= 0)
+        got.update((int(perm[i]), int(perm[j])) for j in row)
+    assert got == ref
+    # one open (non-periodic) system uses the per-atom kernel
+    a, b = off[2], off[3]
+    m.compute(torch.from_numpy(pos[a:b].copy()).cuda(), Z[a:b], None)
+    torch.cuda.synchronize()
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    cnt = m.read(P._lib.NNP_BUF_NBR_COUNT)
+    lists = m.read(P._lib.NNP_BUF_NBR_ANG)
+    I, J = orc.neighbours_fp32(pos[a:b], HCNO["rc_ang"], None)
+    got = set()
+    for i in range(len(perm)):
+        got.update((int(perm[i]), int(perm[j])) for j in lists[i, :cnt[i, 1]])
+    assert got == set(zip(I.tolist(), J.tolist()))
+    m.close()
+
+
 # ------------------------------------------------------------------ batching
 def test_batched_open_systems(P, w_hcno):
     pos, Z, off = sy.walk_batch(12, seed=4)
