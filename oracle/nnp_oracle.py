@@ -321,7 +321,7 @@ def mlp_input_grad(x_np, sigma_c, weights, alpha):
 # Energy and forces.
 # --------------------------------------------------------------------------
 def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=None,
-             centres=None, chunk=2048, forces=True, return_x=False):
+             centres=None, chunk=2048, forces=True, return_x=False, links=None):
     """E_ML and F = -grad E_ML for the NNP atoms of one system (float64).
 
     pos      : [n, 3] positions (float32 values; promoted exactly)
@@ -335,13 +335,31 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
     centres  : optional subset of NNP-local atom indices whose atomic
                energies are summed (E and the gradient then cover only those);
                used to get exact forces on sampled atoms of very large systems.
+    links    : optional (ml_idx, mm_idx, d, Z_link): link atoms placed by eq. 4
+               on the bonds ml -> mm (ml in the index group, mm outside); they
+               are NNP atoms appended after the index group, and their forces
+               reach the ML and MM atoms through the chain rule (autograd
+               through the link positions).
     Returns dict(E, e [centres], F [n, 3], F_mm [m, 3] or None, x (optional)).
     """
     pos = np.asarray(pos)
     n = pos.shape[0]
     idx = np.arange(n) if nnp_idx is None else np.asarray(nnp_idx, dtype=np.int64)
     sigma = species_index(np.asarray(Z)[idx], cfg["species"])
-    sub = torch.tensor(pos[idx].astype(np.float64), requires_grad=forces)
+    full = torch.tensor(pos.astype(np.float64), requires_grad=forces)
+    if links is not None:
+        ml, mmi, d_link, z_link = links
+        ml = np.asarray(ml, dtype=np.int64)
+        mmi = np.asarray(mmi, dtype=np.int64)
+        sigma = np.concatenate([sigma, species_index(np.full(ml.size, z_link), cfg["species"])])
+
+    def nnp_positions():
+        p = full[torch.tensor(idx)]
+        if links is not None and ml.size:
+            rl = link_atom_positions(full[torch.tensor(ml)], full[torch.tensor(mmi)], float(d_link))
+            p = torch.cat([p, rl])
+        return p
+
     mm = None
     if cfg.get("extra_inputs", 0):
         if mm_pos is None:
@@ -349,19 +367,20 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
         mm_t = torch.tensor(np.asarray(mm_pos).astype(np.float64), requires_grad=forces)
         mm = (mm_t, np.asarray(mm_q, np.float64))
     members = weights if isinstance(weights[0][0], list) else [weights]
-    cs_all = np.arange(idx.size) if centres is None else np.asarray(centres, dtype=np.int64)
-    I, J = neighbour_pairs(sub.detach().numpy(), float(cfg["rc_rad"]), box, centres=cs_all)
+    n_nnp = sigma.size
+    cs_all = np.arange(n_nnp) if centres is None else np.asarray(centres, dtype=np.int64)
+    I, J = neighbour_pairs(nnp_positions().detach().numpy(), float(cfg["rc_rad"]), box, centres=cs_all)
     e_all = np.zeros(cs_all.size)
     xs = []
-    grad = torch.zeros_like(sub) if forces else None
+    grad = torch.zeros_like(full) if forces else None
     grad_mm = torch.zeros_like(mm[0]) if (forces and mm is not None) else None
     starts = np.searchsorted(I, cs_all)        # pairs are sorted by centre
     ends = np.searchsorted(I, cs_all, side="right")
     for s in range(0, cs_all.size, chunk):
         c = cs_all[s:s + chunk]
-        lo, hi = starts[s], ends[min(s + chunk, cs_all.size) - 1] if c.size else starts[s]
+        lo, hi = starts[s], ends[min(s + chunk, cs_all.size) - 1]
         pr = (I[lo:hi], J[lo:hi])
-        x = descriptors(sub, sigma, cfg, box=box, centres=c, pairs_rad=pr, mm=mm)
+        x = descriptors(nnp_positions(), sigma, cfg, box=box, centres=c, pairs_rad=pr, mm=mm)
         e = torch.zeros(c.size, dtype=torch.float64)
         for w in members:
             e = e + mlp_energies(x, sigma[c], w, cfg["celu_alpha"])
@@ -370,7 +389,7 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
         if return_x:
             xs.append(x.detach().numpy())
         if forces:
-            targets = [sub] + ([mm[0]] if mm is not None else [])
+            targets = [full] + ([mm[0]] if mm is not None else [])
             gs = torch.autograd.grad(e.sum(), targets, allow_unused=True)
             if gs[0] is not None:
                 grad += gs[0]
@@ -378,9 +397,7 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
                 grad_mm += gs[1]
     out = {"E": math.fsum(e_all.tolist()), "e": e_all}
     if forces:
-        F = np.zeros((n, 3))
-        F[idx] = -grad.numpy()
-        out["F"] = F
+        out["F"] = -grad.numpy()
         out["F_mm"] = (-grad_mm.numpy()) if grad_mm is not None else None
     if return_x:
         out["x"] = np.concatenate(xs) if xs else np.zeros((0, 0))

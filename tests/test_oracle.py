@@ -482,3 +482,54 @@ def test_link_atom_geometry():
     assert abs(np.linalg.norm(rl - r_ml) - 1.0) < 1e-14
     u = (r_mm - r_ml) / np.linalg.norm(r_mm - r_ml)
     assert np.allclose(np.cross(rl - r_ml, u), 0, atol=1e-15)
+
+
+def test_link_atom_defaults_fixture():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "link_atom_defaults.txt")
+    vals = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            vals[k] = float(v)
+    assert vals["link_atom_atomic_number"] == 1
+    d = vals["link_atom_distance_angstrom"]
+    # the oracle's default distance is the paper's default
+    import inspect
+    assert inspect.signature(orc.link_atom_positions).parameters["d"].default == d
+    r_ml = np.array([[0.0, 0.0, 0.0]])
+    r_mm = np.array([[1.53, 0.0, 0.0]])   # a C-C bond cut by the index group
+    rl = orc.link_atom_positions(r_ml, r_mm).numpy()
+    np.testing.assert_allclose(rl, [[1.0, 0.0, 0.0]], atol=1e-15)
+
+
+def test_link_atoms_chain_rule_fd(w_hcno):
+    """Link atoms (eq. 4): forces on the ML and MM atoms of a cut bond match
+    central differences of the energy, and the link force is redistributed
+    without loss (translation invariance of the ML subsystem plus links)."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    pos, Z = sy.walk_molecule(30, rng)
+    pos = pos.astype(np.float64)
+    idx = np.arange(18)                          # the index group cuts the chain
+    d = np.linalg.norm(pos[:, None] - pos[None], axis=-1)
+    ml, mmi = [], []
+    for a in idx:
+        for b in range(18, 30):
+            if d[a, b] < 1.6:
+                ml.append(a)
+                mmi.append(b)
+    assert ml, "test geometry has no cut bond"
+    links = (np.array(ml), np.array(mmi), 1.0, 1)
+    ref = orc.evaluate(pos, Z, HCNO, w_hcno, nnp_idx=idx, links=links)
+    assert np.abs(ref["F"].sum(0)).max() < 1e-10
+    touched = sorted(set(idx) | set(mmi))
+    untouched = [a for a in range(30) if a not in touched]
+    assert np.all(ref["F"][untouched] == 0.0)
+    h = 1e-4
+    for a in (ml[0], mmi[0], idx[3]):
+        for k in range(3):
+            p1 = pos.copy(); p1[a, k] += h
+            p2 = pos.copy(); p2[a, k] -= h
+            fd = -(orc.evaluate(p1, Z, HCNO, w_hcno, nnp_idx=idx, links=links, forces=False)["E"]
+                   - orc.evaluate(p2, Z, HCNO, w_hcno, nnp_idx=idx, links=links, forces=False)["E"]) / (2 * h)
+            assert abs(fd - ref["F"][a, k]) < 2e-7 * max(1.0, abs(ref["F"][a, k])), (a, k)
