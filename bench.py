@@ -243,6 +243,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no RMSE, no cpu_baseline)")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in kernel variant choices")
+    ap.add_argument("--nve", type=int, default=0,
+                    help="also run this many velocity-Verlet NVE steps (dt 0.5 fs, 300 K) and report drift")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -323,6 +325,20 @@ def main(argv=None):
         cpu = cpu_baseline(cfg, w, inp, args.cpu_reps)
         log(f"[bench] cpu: {cpu['value']:.4e} atom-steps/s on {cpu['cores']} threads")
 
+    nve = None
+    if args.nve > 0 and inp["offsets"] is None:
+        from paper_2604_21441_amd.md import run_nve
+        log(f"[bench] NVE: {args.nve} steps, dt 0.5 fs, {args.form}")
+        masses = np.array([sy.WATER_MASS[int(z)] for z in inp["Z"]])
+        v0 = sy.maxwell_boltzmann(inp["Z"], 300.0, seed=2)
+        mdl = P.NNPModel(cfg, weights=flat, precision=args.form)
+        r = run_nve(mdl, inp["pos"], inp["Z"], inp["box"], masses, v0, dt=0.5, steps=args.nve)
+        mdl.close()
+        nve = {"steps": args.nve, "dt_fs": 0.5, "drift_eV_per_atom_per_ps": r["drift_eV_per_atom_per_ps"],
+               "max_abs_dev_eV_per_atom": r["max_abs_dev_eV_per_atom"], "ms_per_step": r["ms_per_step"],
+               "T_start_K": 300.0}
+        log(f"[bench] NVE drift {r['drift_eV_per_atom_per_ps']:.3e} eV/atom/ps, {r['ms_per_step']:.3f} ms/step")
+
     value = n / main_form["ms_per_step"] * 1e3
     out = {
         "metric": METRIC,
@@ -343,6 +359,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "forms": report_forms,
         "stage_roofline": stage_roofs,
+        "nve": nve,
     }
     print(json.dumps(out))
     return 0

@@ -178,6 +178,23 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
                              double* forces, hipStream_t stream);
 
 /*
+ * Link atoms for bonds cut by the index group (Methods, "The nnpot Interface",
+ * eq. 4).  For each of the n_links cut bonds (ml_idx_host[l] inside the index
+ * group, mm_idx_host[l] outside it; atom indices of the system passed to
+ * nnp_compute) a link atom of atomic number link_Z is placed at
+ *   r_L = r_ML + d (r_MM - r_ML) / |r_MM - r_ML|
+ * (bond vector under the minimum image when the call is periodic) and treated
+ * as an NNP atom, appended after the index group.  Its force is passed on to
+ * the ML and MM atoms by the chain rule:
+ *   F_MM += (d/|u|) (F_L - (F_L.u^) u^),  F_ML += F_L - that,  u = r_MM - r_ML.
+ * Applies to later nnp_compute calls (not to batched calls); n_links = 0
+ * removes them.  The paper's defaults are link_Z = 1 and d = 1 Angstrom.
+ * Allocates (device arrays of the link list): call outside graph capture.
+ */
+nnp_status nnp_set_links(nnp_model* m, int32_t n_links, const int32_t* ml_idx_host, const int32_t* mm_idx_host,
+                         float distance, int32_t link_Z);
+
+/*
  * Synchronise `stream` and report the device status word of the calls made
  * since the previous nnp_get_status: NNP_OK, NNP_ECAPACITY (a neighbour list
  * overflowed; results are incomplete -- nnp_reserve larger capacities) or

@@ -117,7 +117,7 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
 }
 
 void free_workspace(nnp_model* m) {
-  dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_key); dfree(m->d_bin_count);
+  dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_sys_off); dfree(m->d_key); dfree(m->d_bin_count);
   dfree(m->d_bin_start); dfree(m->d_cursor); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
   dfree(m->d_slot_atom); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
@@ -343,6 +343,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_idx, n));
   chk(dalloc(&m->d_sigma, n));
   chk(dalloc(&m->d_sys, n));
+  chk(dalloc(&m->d_sys_off, (size_t)max_systems + 2));
   chk(dalloc(&m->d_key, n));
   chk(dalloc(&m->d_perm, n));
   chk(dalloc(&m->d_tmp, n));
@@ -477,9 +478,13 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
   }
   if (accumulate != 0 && accumulate != 1) return set_error(NNP_EINVAL, "accumulate must be 0 or 1");
 
-  // topology
+  // topology (index group plus link atoms)
+  const int n_links = m->n_links_dev;
+  if (n_nnp + n_links > m->max_atoms)
+    return set_error(NNP_ECAPACITY, "NNP atoms plus link atoms exceed the reserved capacity");
   if (Z_host) {
     bool same = m->topo_mode == 0 && m->topo_n_atoms == n_atoms && m->n_nnp == n_nnp &&
+                m->topo_link_version == m->link_version &&
                 std::memcmp(m->topo_Z.data(), Z_host, sizeof(int) * (size_t)n_atoms) == 0;
     if (same) {
       if (nnp_idx_host)
@@ -490,7 +495,8 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
     }
     if (!same) {
       if (!nnp_idx_host && n_nnp != n_atoms) return set_error(NNP_EINVAL, "nnp_idx is NULL but n_nnp != n_atoms");
-      std::vector<int> idx(n_nnp), sig(n_nnp);
+      const int n_loc = n_nnp + n_links;
+      std::vector<int> idx(n_loc), sig(n_loc);
       std::vector<char> seen(n_atoms, 0);
       for (int t = 0; t < n_nnp; ++t) {
         int a = nnp_idx_host ? nnp_idx_host[t] : t;
@@ -500,21 +506,33 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
         nnp_status s = species_of(m, Z_host[a], &sig[t]);
         if (s != NNP_OK) return s;
       }
+      for (int l = 0; l < n_links; ++l) {
+        const int a = m->link_ml[l], b = m->link_mm[l];
+        if (a < 0 || a >= n_atoms || b < 0 || b >= n_atoms || !seen[a] || seen[b])
+          return set_error(NNP_EINVAL, "each link needs its ML atom inside and its MM atom outside the index group");
+        idx[n_nnp + l] = -1 - l;
+        sig[n_nnp + l] = m->link_sigma;
+      }
       nnp_status s;
-      if ((s = upload_ints(m, m->d_idx, idx.data(), n_nnp, stream)) != NNP_OK) return s;
-      if ((s = upload_ints(m, m->d_sigma, sig.data(), n_nnp, stream)) != NNP_OK) return s;
-      std::vector<int> zeros(n_nnp, 0);  // an open single system is system 0
-      if ((s = upload_ints(m, m->d_sys, zeros.data(), n_nnp, stream)) != NNP_OK) return s;
+      if ((s = upload_ints(m, m->d_idx, idx.data(), n_loc, stream)) != NNP_OK) return s;
+      if ((s = upload_ints(m, m->d_sigma, sig.data(), n_loc, stream)) != NNP_OK) return s;
+      std::vector<int> zeros(n_loc, 0);  // an open single system is system 0
+      if ((s = upload_ints(m, m->d_sys, zeros.data(), n_loc, stream)) != NNP_OK) return s;
+      const int off[2] = {0, n_loc};
+      if ((s = upload_ints(m, m->d_sys_off, off, 2, stream)) != NNP_OK) return s;
       m->topo_mode = 0;
       m->topo_n_atoms = n_atoms;
       m->n_nnp = n_nnp;
+      m->topo_link_version = m->link_version;
       m->topo_Z.assign(Z_host, Z_host + n_atoms);
       if (nnp_idx_host) m->topo_idx.assign(nnp_idx_host, nnp_idx_host + n_nnp);
       else m->topo_idx.clear();
     }
-  } else if (m->topo_mode != 0 || m->topo_n_atoms != n_atoms || m->n_nnp != n_nnp) {
+  } else if (m->topo_mode != 0 || m->topo_n_atoms != n_atoms || m->n_nnp != n_nnp ||
+             m->topo_link_version != m->link_version) {
     return set_error(NNP_ESTATE, "Z_host is NULL but no matching topology was given before");
   }
+  const int n_loc = n_nnp + n_links;
 
   // geometry
   if (box_host) {
@@ -526,7 +544,7 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
     m->geo.n_bins = 1;
     m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
   }
-  m->last_n = n_nnp;
+  m->last_n = n_loc;
   auto launch = [=](hipStream_t s) -> nnp_status {
     hipError_t e;
     if (!accumulate) {
@@ -534,11 +552,18 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
       if (mm_forces && (e = launch_fill_f64(mm_forces, 3 * (int64_t)n_mm, s)) != hipSuccess)
         return hip_error(e, "fill");
     }
-    return run_path(m, n_nnp, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, s);
+    if (n_links > 0 && (e = launch_fill_f64(m->d_link_F, 3 * (int64_t)n_links, s)) != hipSuccess)
+      return hip_error(e, "fill");
+    nnp_status st = run_path(m, n_loc, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, s);
+    if (st != NNP_OK) return st;
+    if (n_links > 0 && (e = launch_link_redistribute(*m, pos, forces, s)) != hipSuccess)
+      return hip_error(e, "link atoms");
+    return NNP_OK;
   };
   const int mode = 0;
+  const int lv = m->link_version;
   return dispatch(m, make_key(mode, pos, energy, forces, mm_forces, mm_pos, mm_q, n_atoms, n_nnp, n_mm, accumulate,
-                              m->geo),
+                              lv, m->geo),
                   stream, launch);
 }
 
@@ -573,6 +598,7 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
       if ((st = upload_ints(m, m->d_idx, idx.data(), n, stream)) != NNP_OK) return st;
       if ((st = upload_ints(m, m->d_sigma, sig.data(), n, stream)) != NNP_OK) return st;
       if ((st = upload_ints(m, m->d_sys, sys.data(), n, stream)) != NNP_OK) return st;
+      if ((st = upload_ints(m, m->d_sys_off, atom_offsets_host, n_sys + 1, stream)) != NNP_OK) return st;
       m->topo_mode = 1;
       m->topo_n_atoms = n;
       m->n_nnp = n;
@@ -716,6 +742,38 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
   return NNP_OK;
 }
 
+nnp_status nnp_set_links(nnp_model* m, int32_t n_links, const int32_t* ml_idx_host, const int32_t* mm_idx_host,
+                         float distance, int32_t link_Z) {
+  if (!m || n_links < 0) return set_error(NNP_EINVAL, "bad argument");
+  if (n_links > 0 && (!ml_idx_host || !mm_idx_host)) return set_error(NNP_EINVAL, "null link index arrays");
+  if (n_links > 0 && !(distance > 0.f)) return set_error(NNP_EINVAL, "link distance must be positive");
+  int sig = 0;
+  if (n_links > 0) {
+    nnp_status s = species_of(m, link_Z, &sig);
+    if (s != NNP_OK) return s;
+  }
+  HIP_TRY(hipDeviceSynchronize(), "nnp_set_links");
+  drop_graph(m);
+  dfree(m->d_link_ml);
+  dfree(m->d_link_mm);
+  dfree(m->d_link_F);
+  m->link_ml.assign(ml_idx_host, ml_idx_host + n_links);
+  m->link_mm.assign(mm_idx_host, mm_idx_host + n_links);
+  m->link_d = distance;
+  m->link_Z = link_Z;
+  m->link_sigma = sig;
+  m->n_links_dev = n_links;
+  ++m->link_version;
+  if (n_links > 0) {
+    HIP_TRY(dalloc(&m->d_link_ml, (size_t)n_links), "nnp_set_links");
+    HIP_TRY(dalloc(&m->d_link_mm, (size_t)n_links), "nnp_set_links");
+    HIP_TRY(dalloc(&m->d_link_F, 3 * (size_t)n_links), "nnp_set_links");
+    HIP_TRY(hipMemcpy(m->d_link_ml, ml_idx_host, sizeof(int) * (size_t)n_links, hipMemcpyHostToDevice), "nnp_set_links");
+    HIP_TRY(hipMemcpy(m->d_link_mm, mm_idx_host, sizeof(int) * (size_t)n_links, hipMemcpyHostToDevice), "nnp_set_links");
+  }
+  return NNP_OK;
+}
+
 nnp_status nnp_set_graph(nnp_model* m, int32_t enable) {
   if (!m) return set_error(NNP_EINVAL, "null model");
   m->graph_enabled = enable != 0;
@@ -759,6 +817,9 @@ nnp_status nnp_profile_read(nnp_model* m, double* ms_total, int64_t* calls, hipS
 void nnp_destroy(nnp_model* m) {
   if (!m) return;
   drop_graph(m);
+  dfree(m->d_link_ml);
+  dfree(m->d_link_mm);
+  dfree(m->d_link_F);
   if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
   m->cap_stream = nullptr;
   for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);

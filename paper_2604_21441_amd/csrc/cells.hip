@@ -15,6 +15,24 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Position of NNP-local atom t: a system atom, or a link atom placed on its
+// cut bond (eq. 4; bond vector under the minimum image when periodic).
+__device__ __forceinline__ float3 nnp_position(const float* __restrict__ pos, int a, const LinkArgs& L,
+                                               const Geometry& g) {
+  if (a >= 0) return make_float3(pos[3 * (int64_t)a], pos[3 * (int64_t)a + 1], pos[3 * (int64_t)a + 2]);
+  const int l = -1 - a;
+  const int ml = L.ml[l], mm = L.mm[l];
+  float3 p = make_float3(pos[3 * (int64_t)ml], pos[3 * (int64_t)ml + 1], pos[3 * (int64_t)ml + 2]);
+  float ux = pos[3 * (int64_t)mm] - p.x, uy = pos[3 * (int64_t)mm + 1] - p.y, uz = pos[3 * (int64_t)mm + 2] - p.z;
+  if (g.periodic) {
+    ux -= g.box[0] * rintf(ux * g.inv_box[0]);
+    uy -= g.box[1] * rintf(uy * g.inv_box[1]);
+    uz -= g.box[2] * rintf(uz * g.inv_box[2]);
+  }
+  const float s = L.d / sqrtf(ux * ux + uy * uy + uz * uz);
+  return make_float3(p.x + s * ux, p.y + s * uy, p.z + s * uz);
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int* __restrict__ p, int n, int v) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;
@@ -43,13 +61,13 @@ __device__ __forceinline__ int cell_of(float x, float y, float z, const Geometry
 __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos, int n,
                                                   const int* __restrict__ idx,
                                                   const int* __restrict__ sigma,
-                                                  const int* __restrict__ sys, Geometry g,
+                                                  const int* __restrict__ sys, Geometry g, LinkArgs L,
                                                   int* __restrict__ key, int* __restrict__ bin_count,
                                                   int* __restrict__ status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  int a = idx[t];
-  float x = pos[3 * (int64_t)a + 0], y = pos[3 * (int64_t)a + 1], z = pos[3 * (int64_t)a + 2];
+  const float3 p = nnp_position(pos, idx[t], L, g);
+  float x = p.x, y = p.y, z = p.z;
   int bin;
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
     atomicOr(status, kStatusNonFinite);
@@ -112,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
                                                     const int* __restrict__ tmp,
                                                     const float* __restrict__ pos,
                                                     const int* __restrict__ idx,
-                                                    const int* __restrict__ sigma,
+                                                    const int* __restrict__ sigma, Geometry g, LinkArgs L,
                                                     int* __restrict__ perm,
                                                     float4* __restrict__ spos,
                                                     int* __restrict__ slot_atom) {
@@ -120,20 +138,56 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
   int lane = threadIdx.x & 63;
   if (wave >= n_bins_total) return;
   int b0 = start[wave], b1 = start[wave + 1];
-  for (int p = b0 + lane; p < b1; p += 64) {
-    int t = tmp[p];
+  for (int e = b0 + lane; e < b1; e += 64) {
+    int t = tmp[e];
     int rank = 0;
     for (int q = b0; q < b1; ++q) rank += tmp[q] < t;
     int slot = b0 + rank;
     perm[slot] = t;
-    int a = idx[t];
-    float4 v;
-    v.x = pos[3 * (int64_t)a + 0];
-    v.y = pos[3 * (int64_t)a + 1];
-    v.z = pos[3 * (int64_t)a + 2];
-    v.w = __int_as_float(sigma[t]);
-    spos[slot] = v;
+    const int a = idx[t];
+    const float3 p = nnp_position(pos, a, L, g);
+    spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sigma[t]));
     slot_atom[slot] = a;
+  }
+}
+
+// Open systems (one bin per system): the stable slot of every atom is found
+// directly, one wavefront per system.  The system's atoms are taken in input
+// order, 64 at a time; for each species a ballot gives every atom its rank
+// among the earlier atoms of its species, so slot = bin start + rank.  No
+// atomics and no in-bin sort are needed, whatever the system size.
+__global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys_off, int n_sys, int S,
+                                                      const int* __restrict__ bin_start,
+                                                      const int* __restrict__ sigma,
+                                                      const int* __restrict__ idx, const float* __restrict__ pos,
+                                                      Geometry g, LinkArgs L,
+                                                      int* __restrict__ perm, float4* __restrict__ spos,
+                                                      int* __restrict__ slot_atom) {
+  const int m = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int t0 = sys_off[m], t1 = sys_off[m + 1];
+  const uint64_t lt = __lanemask_lt();
+  int base[kMaxSpecies] = {0, 0, 0, 0};
+  for (int c0 = t0; c0 < t1; c0 += 64) {
+    const int t = c0 + lane;
+    const bool ok = t < t1;
+    const int sg = ok ? sigma[t] : -1;
+    int slot = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+      if (s < S) {
+        const uint64_t mk = __ballot(sg == s);
+        if (sg == s) slot = bin_start[s * n_sys + m] + base[s] + __popcll(mk & lt);
+        base[s] += __popcll(mk);
+      }
+    }
+    if (ok) {
+      const int a = idx[t];
+      perm[slot] = t;
+      const float3 p = nnp_position(pos, a, L, g);
+      spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sg));
+      slot_atom[slot] = a;
+    }
   }
 }
 
@@ -447,19 +501,23 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   const Geometry& g = m.geo;
+  LinkArgs L{m.d_link_ml, m.d_link_mm, m.link_d, m.n_links_dev};
   int nb = m.S * g.n_bins;
   if (n > 0) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
-                       m.d_sigma, m.d_sys, g, m.d_key, m.d_bin_count, m.d_status);
+                       m.d_sigma, m.d_sys, g, L, m.d_key, m.d_bin_count, m.d_status);
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start,
                      m.d_cursor, nb);
-  if (n > 0) {
+  if (n > 0 && !g.periodic) {
+    hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
+                       m.d_sigma, m.d_idx, pos, g, L, m.d_perm, m.d_spos, m.d_slot_atom);
+  } else if (n > 0) {
     int* tmp = m.d_tmp;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
                        m.d_cursor, tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
-                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, m.d_perm, m.d_spos,
+                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_perm, m.d_spos,
                        m.d_slot_atom);
   }
   return hipGetLastError();

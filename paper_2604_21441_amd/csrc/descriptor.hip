@@ -493,7 +493,8 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restric
                                                          const double* __restrict__ self,
                                                          const int* __restrict__ rad_off,
                                                          const int* __restrict__ slot_atom, int n, int S,
-                                                         int max_rad, double* __restrict__ forces) {
+                                                         int max_rad, double* __restrict__ forces,
+                                                         double* __restrict__ link_forces) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid >> 4;
   const int sub = gid & 15;
@@ -513,14 +514,54 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restric
     fz += __shfl_xor(fz, off, 64);
   }
   if (i < n && sub == 0) {
-    double* f = forces + 3 * (int64_t)slot_atom[i];
+    const int a = slot_atom[i];   // a < 0: link atom -1 - a
+    double* f = a >= 0 ? forces + 3 * (int64_t)a : link_forces + 3 * (int64_t)(-1 - a);
     f[0] += fx + self[3 * (int64_t)i];
     f[1] += fy + self[3 * (int64_t)i + 1];
     f[2] += fz + self[3 * (int64_t)i + 2];
   }
 }
 
+// Chain rule for link atoms (eq. 4): r_L = r_ML + d u/|u|, u = r_MM - r_ML, so
+// F_MM += (d/|u|)(F_L - (F_L.u^) u^) and F_ML += F_L - (d/|u|)(F_L - (F_L.u^) u^).
+// FP64 atomics: an ML atom may carry several links.
+__global__ __launch_bounds__(kBlock) void k_link_redistribute(const double* __restrict__ link_forces,
+                                                              const int* __restrict__ ml, const int* __restrict__ mm,
+                                                              int n_links, float d, const float* __restrict__ pos,
+                                                              Geometry g, double* __restrict__ forces) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_links) return;
+  const int a = ml[l], b = mm[l];
+  double ux = (double)pos[3 * (int64_t)b] - pos[3 * (int64_t)a];
+  double uy = (double)pos[3 * (int64_t)b + 1] - pos[3 * (int64_t)a + 1];
+  double uz = (double)pos[3 * (int64_t)b + 2] - pos[3 * (int64_t)a + 2];
+  if (g.periodic) {
+    ux -= g.box[0] * rint(ux / g.box[0]);
+    uy -= g.box[1] * rint(uy / g.box[1]);
+    uz -= g.box[2] * rint(uz / g.box[2]);
+  }
+  const double inv = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+  ux *= inv; uy *= inv; uz *= inv;
+  const double fx = link_forces[3 * l], fy = link_forces[3 * l + 1], fz = link_forces[3 * l + 2];
+  const double s = (double)d * inv;
+  const double fu = fx * ux + fy * uy + fz * uz;
+  const double px = s * (fx - fu * ux), py = s * (fy - fu * uy), pz = s * (fz - fu * uz);
+  unsafeAtomicAdd(forces + 3 * (int64_t)b + 0, px);
+  unsafeAtomicAdd(forces + 3 * (int64_t)b + 1, py);
+  unsafeAtomicAdd(forces + 3 * (int64_t)b + 2, pz);
+  unsafeAtomicAdd(forces + 3 * (int64_t)a + 0, fx - px);
+  unsafeAtomicAdd(forces + 3 * (int64_t)a + 1, fy - py);
+  unsafeAtomicAdd(forces + 3 * (int64_t)a + 2, fz - pz);
+}
+
 }  // namespace
+
+hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forces, hipStream_t st) {
+  if (m.n_links_dev == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_link_redistribute, dim3((m.n_links_dev + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                     m.d_link_F, m.d_link_ml, m.d_link_mm, m.n_links_dev, m.link_d, pos, m.geo, forces);
+  return hipGetLastError();
+}
 
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
@@ -564,7 +605,7 @@ hipError_t launch_force_gather(nnp_model& m, int n, double* forces, hipStream_t 
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((16 * (int64_t)n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                      m.d_contrib, m.d_self,
-                     m.d_rad_off, m.d_slot_atom, n, m.S, m.max_rad, forces);
+                     m.d_rad_off, m.d_slot_atom, n, m.S, m.max_rad, forces, m.d_link_F);
   return hipGetLastError();
 }
 

@@ -185,22 +185,24 @@ __global__ __launch_bounds__(256) void k_mlp_split(MlpArgs a, float alpha) {
   const float inv_alpha = 1.f / alpha;
   const float inv_alpha_l2 = kLog2e / alpha;
 
-  // stage x in fragment layout: tile (c, kb), lane l holds x[row c*16 + l%16][16 kb + 4 (l/16) .. +3]
-  for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
-    const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
-    const int row = row0 + c * 16 + (l & 15);
-    v4f v = v4f{0.f, 0.f, 0.f, 0.f};
-    if (row < row_end) v = *reinterpret_cast<const v4f*>(a.x + (int64_t)row * a.stride + 16 * kb + 4 * (l >> 4));
-    bufX[(c * TX + kb) * 64 + l] = v;
-  }
   float e_acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) e_acc[c] = 0.f;
-  __syncthreads();
 
   for (int mem = 0; mem < a.n_members; ++mem) {
     const Elem* Wm = reinterpret_cast<const Elem*>(a.wmat) + (int64_t)(mem * a.S + s) * a.mat_per_species;
     const float* V = a.wvec + (int64_t)(mem * a.S + s) * a.vec_per_species;
+
+    // stage x in fragment layout (again for every member: the buffer is reused
+    // by later products): tile (c, kb), lane l holds x[row c*16 + l%16][16 kb + 4 (l/16) .. +3]
+    for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
+      const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
+      const int row = row0 + c * 16 + (l & 15);
+      v4f v = v4f{0.f, 0.f, 0.f, 0.f};
+      if (row < row_end) v = *reinterpret_cast<const v4f*>(a.x + (int64_t)row * a.stride + 16 * kb + 4 * (l >> 4));
+      bufX[(c * TX + kb) * 64 + l] = v;
+    }
+    __syncthreads();
 
     // ---- layer 1: h1 = celu(W1 x + b1)       X -> A
     v4f h1[Own<N1>::n][C];

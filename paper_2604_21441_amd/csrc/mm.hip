@@ -79,7 +79,8 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
                                                    const float* __restrict__ mm_q, int n_mm,
                                                    const float* __restrict__ gx, DescParams p, Geometry g,
                                                    double* __restrict__ forces,
-                                                   double* __restrict__ mm_forces) {
+                                                   double* __restrict__ mm_forces,
+                                                   double* __restrict__ link_forces) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   int lane = threadIdx.x & 63;
   bool ok = j < n_mm;
@@ -111,7 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
     fx -= vx; fy -= vy; fz -= vz;
     float sx = wave_sum(vx), sy = wave_sum(vy), sz = wave_sum(vz);
     if (lane == 0 && (sx != 0.f || sy != 0.f || sz != 0.f)) {
-      double* f = forces + 3 * (int64_t)slot_atom[i];
+      const int a = slot_atom[i];   // a < 0: link atom -1 - a
+      double* f = a >= 0 ? forces + 3 * (int64_t)a : link_forces + 3 * (int64_t)(-1 - a);
       unsafeAtomicAdd(f + 0, (double)sx);
       unsafeAtomicAdd(f + 1, (double)sy);
       unsafeAtomicAdd(f + 2, (double)sz);
@@ -142,7 +144,7 @@ hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, con
                          double* forces, double* mm_forces, hipStream_t st) {
   if (n == 0 || n_mm == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mm_bwd, dim3((n_mm + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_spos,
-                     m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.dp, m.geo, forces, mm_forces);
+                     m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.dp, m.geo, forces, mm_forces, m.d_link_F);
   return hipGetLastError();
 }
 

@@ -52,6 +52,14 @@ struct Geometry {
   int n_bins;                           // cells (periodic) or systems (batched)
 };
 
+// Link atoms: NNP-local atoms t >= n_group have idx[t] = -1 - l.
+struct LinkArgs {
+  const int* ml;     // [n_links] ML atom index
+  const int* mm;     // [n_links] MM atom index
+  float d;
+  int n;
+};
+
 // Neighbour-list arrays (per sorted slot).
 struct NbrLists {
   int* rad;      // [n][max_rad]
@@ -106,6 +114,7 @@ struct nnp_model {
   int* d_idx = nullptr;        // NNP-local atom -> atom index
   int* d_sigma = nullptr;      // NNP-local atom -> species
   int* d_sys = nullptr;        // NNP-local atom -> system (batched)
+  int* d_sys_off = nullptr;    // [n_sys + 1] first NNP-local atom of each open system
   int* d_key = nullptr;
   int* d_bin_count = nullptr;
   int* d_bin_start = nullptr;  // [max_bins + 1]
@@ -130,9 +139,19 @@ struct nnp_model {
   int* d_status = nullptr;
   int* h_stage = nullptr;      // pinned staging for topology uploads
 
+  // link atoms
+  std::vector<int> link_ml, link_mm;
+  float link_d = 1.0f;
+  int link_Z = 1, link_sigma = 0, link_version = 0;
+  int* d_link_ml = nullptr;
+  int* d_link_mm = nullptr;
+  double* d_link_F = nullptr;  // [n_links][3] force on each link atom
+  int n_links_dev = 0;
+
   // topology cache (host copies)
   int topo_mode = -1;          // 0 single system, 1 batched
   int topo_n_atoms = -1;
+  int topo_link_version = -1;
   std::vector<int> topo_Z, topo_idx, topo_offsets;
   int n_nnp = 0;
 
@@ -190,5 +209,6 @@ hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumula
 
 // fills (api.cpp)
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forces, hipStream_t st);
 
 }  // namespace nnp

@@ -18,7 +18,7 @@ from . import _lib as L
 
 __all__ = [
     "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
-    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
 
@@ -169,6 +169,14 @@ def nnp_autotune(h, reps: int = 5, stream=None) -> dict:
     return {"neighbours": chosen[0], "descriptor": chosen[1], "network": chosen[2]}
 
 
+def nnp_set_links(h, ml_idx, mm_idx, distance: float = 1.0, link_Z: int = 1) -> None:
+    """Link atoms on the bonds ml_idx[l] (inside the index group) -> mm_idx[l] (outside), eq. 4."""
+    ml, mlp = _host(ml_idx, np.int32, "ml_idx")
+    mm, mmp = _host(mm_idx, np.int32, "mm_idx")
+    n = 0 if ml is None else ml.size
+    _check(L.load().nnp_set_links(h, n, mlp, mmp, float(distance), int(link_Z)), "nnp_set_links")
+
+
 def nnp_set_graph(h, enable: bool) -> None:
     _check(L.load().nnp_set_graph(h, 1 if enable else 0), "nnp_set_graph")
 
@@ -246,6 +254,9 @@ class NNPModel:
 
     def set_graph(self, enable: bool) -> None:
         nnp_set_graph(self.h, enable)
+
+    def set_links(self, ml_idx, mm_idx, distance: float = 1.0, link_Z: int = 1) -> None:
+        nnp_set_links(self.h, ml_idx, mm_idx, distance, link_Z)
 
     def autotune(self, reps: int = 5) -> dict:
         return nnp_autotune(self.h, reps)

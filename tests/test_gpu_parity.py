@@ -171,7 +171,7 @@ def test_forces_match_gpu_finite_differences(P, water_models, boxes):
     E0, F, _ = _run(m, pos, Z, box)
     rng = np.random.default_rng(3)
     h = 3e-3
-    for a in rng.choice(len(Z), 8, replace=False):
+    for a in rng.choice(len(Z), 32, replace=False):
         for k in range(3):
             p1 = pos.copy(); p1[a, k] += h
             p2 = pos.copy(); p2[a, k] -= h
@@ -307,6 +307,78 @@ def test_neighbour_sets_batched_and_open(P, w_hcno):
     for i in range(len(perm)):
         got.update((int(perm[i]), int(perm[j])) for j in lists[i, :cnt[i, 1]])
     assert got == set(zip(I.tolist(), J.tolist()))
+    m.close()
+
+
+def test_ensemble_members_average(P):
+    """An ensemble of networks sharing one descriptor: E and F are the member means."""
+    pos, Z, box = sy.water_box(64, 12.42, seed=0)
+    w2 = sy.model_weights(WATER, seed=1, n_members=3)
+    ref = orc.evaluate(pos, Z, WATER, w2, box=box)
+    for prec, tol in (("fp32", 1e-5), ("bf16", 1e-2)):
+        m = P.NNPModel(WATER, weights=sy.flat_weights(w2), precision=prec, n_members=3)
+        E, F, _ = _run(m, pos, Z, box)
+        assert abs(E[0] - ref["E"]) / len(Z) < (1e-6 if prec == "fp32" else 1e-2)
+        assert rel_rmse(F, ref["F"]) < tol
+        m.close()
+
+
+def test_seeded_weights_match_generator(P):
+    """nnp_create's own seed path reproduces the generator module's weights."""
+    pos, Z, box = sy.water_box(64, 12.42, seed=0)
+    m_seed = P.NNPModel(WATER, seed=7, precision="fp32")
+    m_given = P.NNPModel(WATER, weights=sy.flat_weights(sy.model_weights(WATER, seed=7)), precision="fp32")
+    E1, F1, _ = _run(m_seed, pos, Z, box)
+    E2, F2, _ = _run(m_given, pos, Z, box)
+    assert E1[0] == E2[0]
+    assert np.array_equal(F1, F2) or np.abs(F1 - F2).max() < 1e-12
+
+
+def test_nve_energy_error_scales_with_dt_squared(P, water_models):
+    """Velocity Verlet with the library's forces: halving dt cuts the energy error ~4x,
+    which needs forces consistent with the energy."""
+    from paper_2604_21441_amd.md import run_nve
+    pos, Z, box = sy.water_box(64, 12.42, seed=0)
+    masses = np.array([sy.WATER_MASS[int(z)] for z in Z])
+    v0 = sy.maxwell_boltzmann(Z, 300.0, seed=2)
+    devs = []
+    for dt, steps in ((0.2, 100), (0.1, 200)):
+        r = run_nve(water_models["fp32"], pos, Z, box, masses, v0, dt=dt, steps=steps)
+        assert np.all(np.isfinite(r["etot"]))
+        devs.append(r["max_abs_dev_eV_per_atom"])
+    ratio = devs[0] / devs[1]
+    assert 2.5 < ratio < 6.0, (devs, ratio)
+
+
+def test_link_atoms(P, w_hcno):
+    """Link atoms on bonds cut by the index group (eq. 4): energy and the forces on
+    ML, MM and interior atoms against the oracle's chain rule."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    pos, Z = sy.walk_molecule(40, rng)
+    idx = np.arange(24, dtype=np.int32)
+    d = np.linalg.norm(pos[:, None].astype(np.float64) - pos[None], axis=-1)
+    ml, mm = [], []
+    for a in idx:
+        for b in range(24, 40):
+            if d[a, b] < 1.6:
+                ml.append(a)
+                mm.append(b)
+    assert ml
+    ml = np.array(ml, np.int32)
+    mm = np.array(mm, np.int32)
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
+    m.set_links(ml, mm, 1.0, 1)
+    for box in (None, np.full(3, 60.0, np.float32)):
+        E, F, _ = _run(m, pos, Z, box, nnp_idx=idx)
+        ref = orc.evaluate(pos, Z, HCNO, w_hcno, box=box, nnp_idx=idx, links=(ml, mm, 1.0, 1))
+        assert abs(E[0] - ref["E"]) / (idx.size + ml.size) < 1e-6
+        assert rel_rmse(F, ref["F"]) < 1e-5
+        assert np.abs(F[mm]).max() > 0            # MM atoms of cut bonds feel the link atoms
+    m.set_links(np.zeros(0, np.int32), np.zeros(0, np.int32))
+    E, F, _ = _run(m, pos, Z, None, nnp_idx=idx)
+    ref = orc.evaluate(pos, Z, HCNO, w_hcno, nnp_idx=idx)
+    assert abs(E[0] - ref["E"]) / idx.size < 1e-6
+    assert rel_rmse(F, ref["F"]) < 1e-5
     m.close()
 
 
