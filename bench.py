@@ -56,8 +56,162 @@ OPS_BWD_RAD_PAIR = 200
 OPS_BWD_TRIPLET = 300
 
 
+# rocprofv3 summaries committed under profiles/ (written by --summarize-profiles).
+PROFILE_TAGS = {"c1": "water192", "c2": "water12288", "c3": "water98304", "c5a": "water261000",
+                "c4": "hcno_batch256"}
+CSRC = os.path.join(ROOT, "paper_2604_21441_amd", "csrc")
+CALIB_BYTES = 1 << 30   # --calib-copy: one device copy of this many bytes (read + write)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources():
+    """Kernel base name -> defining source file and a digest of that file, the shared
+    header and the build script (a profile's counters are stale once these change)."""
+    import glob
+    import hashlib
+    import re
+    common = b"".join(open(f, "rb").read() for f in (os.path.join(CSRC, "nnp_internal.h"),
+                                                     os.path.join(ROOT, "paper_2604_21441_amd", "build.py")))
+    out = {}
+    for f in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        src = open(f, "rb").read()
+        dig = hashlib.sha256(src + common).hexdigest()[:16]
+        for m in re.finditer(rb"__global__\s+(?:__launch_bounds__\([^)]*\)\s+)?void\s+(k_\w+)\s*\(", src):
+            out[m.group(1).decode()] = {"file": os.path.basename(f), "digest": dig}
+    return out
+
+
+def stage_kernel(stage, variants, prec, cfg, periodic=True):
+    """Name (as the profiler prints it, without namespaces and arguments) of the kernel
+    that runs a stage, given the variants the library reports."""
+    widths = list(cfg["widths"])
+    k0 = (widths[0] + 31) // 32 * 32
+    bf = "true" if prec == "bf16" else "false"
+    v = variants or {}
+    if stage == "neighbours":
+        return ["k_neighbours", "k_neighbours_cell"][v.get("neighbours", 0)]
+    if stage == "descriptor":
+        return ["k_desc_fwd", "k_desc_fwd_rows"][v.get("descriptor", 1)]
+    if stage == "network":
+        nv = v.get("network", 1)
+        dims = f"{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {bf}"
+        return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {nv}>"
+    return {"adjoint": "k_desc_bwd", "gather": "k_force_gather",
+            "energy": "k_energy_final" if periodic else "k_energy"}.get(stage)
+
+
+def profile_traffic(workload, kernel):
+    """HBM bytes per dispatch (calibrated FETCH_SIZE + WRITE_SIZE) of a kernel from the
+    committed profile of this workload, or None if absent or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"nnp_compute_{PROFILE_TAGS[workload]}_traffic.json")
+    if kernel is None or not os.path.exists(path):
+        return None
+    k = json.load(open(path))["kernels"].get(kernel)
+    if not k or k.get("fetch_bytes") is None or k.get("write_bytes") is None:
+        return None
+    src = kernel_sources().get(kernel.split("<")[0])
+    if src is None or src["digest"] != k.get("digest"):
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+def profile_commands(workload):
+    """The commands that produce the rocprofv3 output --summarize-profiles reads
+    ($ROOT = repository root, $OUT = output folder)."""
+    b = "python3 $ROOT/bench.py"
+    return [
+        "cd /tmp && export TMPDIR=/tmp",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/kt_{workload} -o run -- "
+        f"{b} --workload {workload} --steps 20 --warmup 5 --no-cpu",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/FETCH_SIZE_{workload} -o run -- "
+        f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/WRITE_SIZE_{workload} -o run -- "
+        f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/calib_FETCH_SIZE -o run -- {b} --calib-copy",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/calib_WRITE_SIZE -o run -- {b} --calib-copy",
+        f"python3 bench.py --summarize-profiles $OUT --workload {workload}",
+    ]
+
+
+def _short_name(name):
+    s = name.replace("void ", "").replace("nnp::(anonymous namespace)::", "").strip()
+    depth = 0
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return s[:i]
+    return s
+
+
+def _counter_means(path):
+    """Mean counter value per kernel (over dispatches) from a counter_collection CSV."""
+    import csv
+    import collections
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        acc[(_short_name(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def summarize_profiles(out_dir, workload):
+    """Write <out_dir>/profiles/nnp_compute_<tag>_kernels.md and _traffic.json from the
+    rocprofv3 output under out_dir.  Run it on the tree that was profiled: the source
+    digests it records are those of the files present when it runs."""
+    import csv
+    tag = PROFILE_TAGS[workload]
+    stats = list(csv.DictReader(open(os.path.join(out_dir, f"kt_{workload}", "run_kernel_stats.csv"))))
+    calib = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        means = _counter_means(os.path.join(out_dir, f"calib_{c}", "run_counter_collection.csv"))
+        kib = max(v for (k, cn), (v, _) in means.items() if "copyBuffer" in k and cn == c)
+        calib[c] = CALIB_BYTES / (kib * 1024.0)       # bytes per counted byte
+    counters = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        for (k, cn), (v, nd) in _counter_means(os.path.join(out_dir, f"{c}_{workload}",
+                                                            "run_counter_collection.csv")).items():
+            counters.setdefault(k, {})[c] = v * 1024.0 * calib[c]
+    srcs = kernel_sources()
+    kernels = {}
+    for r in stats:
+        k = _short_name(r["Name"])
+        if not k.startswith("k_"):
+            continue
+        src = srcs.get(k.split("<")[0], {})
+        kernels[k] = {"calls": int(r["Calls"]), "avg_us": float(r["AverageNs"]) / 1e3,
+                      "min_us": float(r["MinNs"]) / 1e3, "max_us": float(r["MaxNs"]) / 1e3,
+                      "share_pct": float(r["Percentage"]),
+                      "fetch_bytes": counters.get(k, {}).get("FETCH_SIZE"),
+                      "write_bytes": counters.get(k, {}).get("WRITE_SIZE"),
+                      "source": src.get("file"), "digest": src.get("digest")}
+    cmds = profile_commands(workload)
+    doc = {"workload": WORKLOADS[workload]["desc"], "calibration": calib, "commands": cmds, "kernels": kernels}
+    dest = os.path.join(out_dir, "profiles")
+    os.makedirs(dest, exist_ok=True)
+    with open(os.path.join(dest, f"nnp_compute_{tag}_traffic.json"), "w") as f:
+        json.dump(doc, f, indent=1)
+    lines = [f"# Kernel durations and HBM traffic: {WORKLOADS[workload]['desc']}", "",
+             "rocprofv3 kernel-trace statistics (every dispatch of the run: autotuning candidates, the",
+             "FP32 and BF16 forms, graph replays and the event-timed pass) and per-dispatch HBM bytes",
+             "from FETCH_SIZE / WRITE_SIZE, scaled by what the same counters read for a plain",
+             f"{CALIB_BYTES >> 20} MiB device copy (fetch x{calib['FETCH_SIZE']:.3f}, "
+             f"write x{calib['WRITE_SIZE']:.3f}).", "", "Commands ($ROOT = repository root, $OUT = output folder):",
+             "", "```"] + cmds + ["```", "",
+             "| kernel | calls | avg us | min us | max us | % time | fetch MB | write MB | source |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---|"]
+    for k, e in sorted(kernels.items(), key=lambda kv: -kv[1]["share_pct"]):
+        fb = "" if e["fetch_bytes"] is None else f"{e['fetch_bytes'] / 1e6:.2f}"
+        wb = "" if e["write_bytes"] is None else f"{e['write_bytes'] / 1e6:.2f}"
+        lines.append(f"| `{k}` | {e['calls']} | {e['avg_us']:.2f} | {e['min_us']:.2f} | {e['max_us']:.2f} | "
+                     f"{e['share_pct']:.2f} | {fb} | {wb} | {e['source']} |")
+    with open(os.path.join(dest, f"nnp_compute_{tag}_kernels.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log(f"[bench] wrote {dest}/nnp_compute_{tag}_kernels.md and _traffic.json ({len(kernels)} kernels)")
 
 
 def network_flops_per_atom(widths):
@@ -110,7 +264,9 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
         raise RuntimeError(f"device status {st} after the first call")
     E_first = E.detach().cpu().numpy().astype(float)
     F_first = F.detach().cpu().numpy()
-    tuned = m.autotune(5) if autotune else None
+    if autotune:
+        m.autotune(10)
+    tuned = m.variants()
     for _ in range(warmup):
         call()
     torch.cuda.synchronize()
@@ -201,16 +357,19 @@ def cpu_baseline(cfg, w, inp, reps):
             "sample": sample, "seconds_per_eval": t}
 
 
-def roofline(res, widths, prec, stage):
+def roofline(res, cfg, prec, stage, workload, periodic):
     """Roofline entry for one stage from its live event time and its algorithmic work."""
+    widths = list(cfg["widths"])
+    kernel = stage_kernel(stage, res["tuned"], prec, cfg, periodic)
+    traffic = profile_traffic(workload, kernel)
     n = res["n"]
     t = res["stage_ms"][stage] * 1e-3
     D = widths[0]
     if stage == "network":
         flops = network_flops_per_atom(widths) * n
         ach = flops / t / 1e12
-        return {"kernel": "k_mlp", "bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_TFLOPS[prec],
-                "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_TFLOPS[prec], "traffic": None,
+        return {"kernel": kernel, "bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_TFLOPS[prec],
+                "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_TFLOPS[prec], "traffic": traffic,
                 "algorithmic_per_launch": flops}
     if stage in ("adjoint", "descriptor"):
         if stage == "adjoint":
@@ -220,17 +379,17 @@ def roofline(res, widths, prec, stage):
             ops = OPS_FWD_RAD_PAIR * res["rad_pairs"] + OPS_FWD_TRIPLET * res["triplets"]
             byts = n * (16 + 4 * D)
         ach = ops / t / 1e12
-        return {"kernel": "k_desc_bwd" if stage == "adjoint" else "k_desc_fwd", "bound": "alu",
+        return {"kernel": kernel, "bound": "alu",
                 "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
-                "traffic": None, "algorithmic_per_launch": ops, "hbm_GBs": byts / t / 1e9}
+                "traffic": traffic, "algorithmic_per_launch": ops, "hbm_GBs": byts / t / 1e9}
     # memory-bound stages
     byts = {"neighbours": n * 16 + 4 * res["rad_pairs"] + 8 * res["rad_pairs"],
             "gather": 16 * res["rad_pairs"] + 24 * n + 48 * n,
             "cells": 16 * n + 16 * n,
             "energy": 8 * (n // 16)}.get(stage, 16 * n)
     ach = byts / t / 1e9
-    return {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBS, "traffic": None, "algorithmic_per_launch": byts}
+    return {"kernel": kernel or stage, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "algorithmic_per_launch": byts}
 
 
 def main(argv=None):
@@ -245,10 +404,15 @@ def main(argv=None):
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in kernel variant choices")
     ap.add_argument("--nve", type=int, default=0,
                     help="also run this many velocity-Verlet NVE steps (dt 0.5 fs, 300 K) and report drift")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write DIR/profiles/ summaries for --workload from rocprofv3 output under DIR, then exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args(argv)
 
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload)
+        return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path.", file=sys.stderr)
@@ -263,7 +427,7 @@ def main(argv=None):
     import paper_2604_21441_amd as P
 
     if args.calib_copy:
-        nbytes = 1 << 30
+        nbytes = CALIB_BYTES
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(5):
@@ -316,8 +480,10 @@ def main(argv=None):
 
     main_form = forms[args.form]
     dom = max(main_form["stage_ms"], key=lambda k: main_form["stage_ms"][k])
-    roof = roofline(main_form, widths, args.form, dom)
-    stage_roofs = {s: roofline(main_form, widths, args.form, s) for s in ("descriptor", "network", "adjoint")}
+    periodic = inp["offsets"] is None
+    roof = roofline(main_form, cfg, args.form, dom, args.workload, periodic)
+    stage_roofs = {s: roofline(main_form, cfg, args.form, s, args.workload, periodic)
+                   for s in ("descriptor", "network", "adjoint")}
 
     cpu = None
     if not args.no_cpu:

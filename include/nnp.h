@@ -235,12 +235,38 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
  * (same size and geometry) and keeps the fastest for that size bucket
  * (quarter octaves of the atom count); later calls of that size use it.
  * chosen (host, [3] or NULL) receives the variants now used for the
- * neighbour, descriptor and network stages (-1: built-in default).
+ * neighbour, descriptor and network stages, as nnp_get_variants.
  * Synchronises the stream; drops the cached graph.  If the environment
  * variable NNP_TUNE_CACHE names a file, results are appended to it and
  * read back by nnp_create for the same GPU architecture and model shape.
  */
 nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t stream);
+
+/* Stages with kernel variants (index of `chosen` above, `stage` below). */
+typedef enum {
+  NNP_TUNE_NEIGHBOURS = 0,
+  NNP_TUNE_DESCRIPTOR = 1,
+  NNP_TUNE_NETWORK = 2
+} nnp_tune_stage;
+
+/*
+ * Pin the kernel variant of one stage for later calls, overriding the tuned
+ * choice and the built-in default; variant = -1 removes the pin.  Variants:
+ * neighbours 0 one wavefront per atom, 1 one wavefront per cell (periodic
+ * boxes; other geometries use 0); descriptor forward 0 one wavefront per
+ * atom, 1 one 16-lane row per atom; network 0 register-resident wavefronts,
+ * 1 / 2 row-split workgroups of 16 / 32 atoms.  All variants compute the same
+ * quantities (integer stages bit-identically, floating point to rounding).
+ * Drops the cached graph.  NNP_EINVAL for an unknown stage or variant.
+ */
+nnp_status nnp_set_variant(nnp_model* m, int32_t stage, int32_t variant);
+
+/*
+ * The kernel variants (chosen[3], host, indexed by nnp_tune_stage) that a
+ * call of the size and geometry of the previous compute call runs: pinned,
+ * else tuned, else the built-in default.  NNP_ESTATE before the first call.
+ */
+nnp_status nnp_get_variants(nnp_model* m, int32_t* chosen);
 
 /*
  * HIP-graph replay (enabled by default).  The first call of a configuration
@@ -264,9 +290,10 @@ typedef enum {
   NNP_STAGE_DESCRIPTOR = 2, /* descriptor forward                            */
   NNP_STAGE_MM = 3,         /* MM potential channel forward                  */
   NNP_STAGE_NETWORK = 4,    /* per-species networks, forward + backward      */
-  NNP_STAGE_ENERGY = 5,     /* FP64 energy reduction                         */
+  NNP_STAGE_ENERGY = 5,     /* (reads 0: the FP64 energy reduction runs in
+                               the gather's launch, timed as GATHER)         */
   NNP_STAGE_ADJOINT = 6,    /* descriptor adjoint                            */
-  NNP_STAGE_GATHER = 7,     /* FP64 force gather                             */
+  NNP_STAGE_GATHER = 7,     /* FP64 force gather and energy reduction        */
   NNP_STAGE_MM_ADJOINT = 8, /* MM channel adjoint                            */
   NNP_STAGE_COUNT = 9
 } nnp_stage;

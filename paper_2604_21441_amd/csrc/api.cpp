@@ -33,6 +33,12 @@ int tuned_choice(const nnp_model& m, int stage, int n) {
   return it == m.tuned.end() ? -1 : it->second;
 }
 
+int stage_variant(const nnp_model& m, int stage, int n) {
+  if (m.force_variant[stage] >= 0) return m.force_variant[stage];
+  if (m.pinned[stage] >= 0) return m.pinned[stage];
+  return tuned_choice(m, stage, n);
+}
+
 namespace {
 
 #define HIP_TRY(expr, what)                      \
@@ -275,6 +281,15 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
     p.cos_sect[k] = (float)std::cos((double)cfg->ang_sect_host[k]);
     p.sin_sect[k] = (float)std::sin((double)cfg->ang_sect_host[k]);
   }
+  {
+    const double l2e = 1.4426950408889634;
+    const double sr = std::sqrt((double)cfg->eta_rad * l2e), sa = std::sqrt((double)cfg->eta_ang * l2e);
+    p.sq_eta_r = (float)sr;
+    p.hq_eta_a = (float)(0.5 * sa);
+    p.sq_pref = (float)std::pow(2.0, 0.5 * (1.0 - (double)cfg->zeta));
+    for (int k = 0; k < kRadShifts; ++k) p.rad_shift_s[k] = (float)(sr * (double)cfg->rad_shift_host[k]);
+    for (int k = 0; k < kAngShifts; ++k) p.ang_shift_s[k] = (float)(sa * (double)cfg->ang_shift_host[k]);
+  }
   p.mm_cutoff = cfg->mm_cutoff;
   p.ke = (float)cfg->ke_coulomb;
   p.S = S;
@@ -440,7 +455,7 @@ struct StageTimer {
 
 nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float* mm_pos, const float* mm_q,
                     double* energies, int n_sys, double* forces, double* mm_forces, int accumulate,
-                    hipStream_t st) {
+                    int assign_forces, hipStream_t st) {
   m->last_n = n;
   StageTimer tm(m, st);
   STAGE(NNP_STAGE_CELLS, launch_cells(*m, pos, n, st), "cell list");
@@ -448,9 +463,9 @@ nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float
   STAGE(NNP_STAGE_DESCRIPTOR, launch_descriptor_fwd(*m, n, st), "descriptor");
   if (m->extra) STAGE(NNP_STAGE_MM, launch_mm_fwd(*m, n, n_mm, mm_pos, mm_q, st), "mm channel");
   STAGE(NNP_STAGE_NETWORK, launch_mlp(*m, n, st), "network");
-  STAGE(NNP_STAGE_ENERGY, launch_energy(*m, n_sys, energies, accumulate, st), "energy");
   STAGE(NNP_STAGE_ADJOINT, launch_descriptor_bwd(*m, n, st), "descriptor adjoint");
-  STAGE(NNP_STAGE_GATHER, launch_force_gather(*m, n, forces, st), "force gather");
+  STAGE(NNP_STAGE_GATHER, launch_force_gather(*m, n, forces, assign_forces, energies, n_sys, accumulate, st),
+        "force gather and energy");
   if (m->extra)
     STAGE(NNP_STAGE_MM_ADJOINT, launch_mm_bwd(*m, n, n_mm, mm_pos, mm_q, forces, mm_forces, st), "mm adjoint");
   tm.done();
@@ -547,14 +562,18 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
   m->last_n = n_loc;
   auto launch = [=](hipStream_t s) -> nnp_status {
     hipError_t e;
+    // with every atom in the index group the gather overwrites each force row
+    const int assign = !accumulate && n_nnp == n_atoms;
     if (!accumulate) {
-      if ((e = launch_fill_f64(forces, 3 * (int64_t)n_atoms, s)) != hipSuccess) return hip_error(e, "fill");
+      if (!assign && (e = launch_fill_f64(forces, 3 * (int64_t)n_atoms, s)) != hipSuccess)
+        return hip_error(e, "fill");
       if (mm_forces && (e = launch_fill_f64(mm_forces, 3 * (int64_t)n_mm, s)) != hipSuccess)
         return hip_error(e, "fill");
     }
     if (n_links > 0 && (e = launch_fill_f64(m->d_link_F, 3 * (int64_t)n_links, s)) != hipSuccess)
       return hip_error(e, "fill");
-    nnp_status st = run_path(m, n_loc, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, s);
+    nnp_status st =
+        run_path(m, n_loc, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, assign, s);
     if (st != NNP_OK) return st;
     if (n_links > 0 && (e = launch_link_redistribute(*m, pos, forces, s)) != hipSuccess)
       return hip_error(e, "link atoms");
@@ -616,9 +635,8 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
   if (m->S * n_sys > m->max_bins) return set_error(NNP_ECAPACITY, "too many systems for the reserved bins");
   m->last_n = n;
   auto launch = [=](hipStream_t s) -> nnp_status {
-    hipError_t e;
-    if ((e = launch_fill_f64(forces, 3 * (int64_t)n, s)) != hipSuccess) return hip_error(e, "fill");
-    return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, s);
+    // every atom of a batched call is an NNP atom: the gather overwrites each force row
+    return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, 1, s);
   };
   const int mode = 1;
   return dispatch(m, make_key(mode, pos, energies, forces, n, n_sys, m->geo), stream, launch);
@@ -704,7 +722,9 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
     m->force_variant[stage] = v;
     hipError_t e = hipSuccess;
     auto run = [&]() {
-      return stage == kTuneNetwork ? launch_mlp(*m, n, stream) : launch_neighbours(*m, n, stream);
+      return stage == kTuneNetwork      ? launch_mlp(*m, n, stream)
+             : stage == kTuneDescriptor ? launch_descriptor_fwd(*m, n, stream)
+                                        : launch_neighbours(*m, n, stream);
     };
     e = run();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, stream);
@@ -715,10 +735,11 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
     m->force_variant[stage] = -1;
     return e == hipSuccess ? NNP_OK : hip_error(e, "nnp_autotune");
   };
-  const int stages[2] = {kTuneNetwork, kTuneNeighbours};
+  const int stages[3] = {kTuneNetwork, kTuneDescriptor, kTuneNeighbours};
   nnp_status status = NNP_OK;
   for (int st : stages) {
-    int nv = st == kTuneNetwork ? 3 : (m->geo.n_bins >= 2 ? 2 : 1);
+    if (m->pinned[st] >= 0) continue;   // a pinned stage keeps its variant
+    int nv = st == kTuneNeighbours && m->geo.n_bins < 2 ? 1 : kStageVariants[st];
     int best = 0;
     float best_ms = 0.f;
     for (int v = 0; v < nv && status == NNP_OK; ++v) {
@@ -735,10 +756,16 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (status != NNP_OK) return status;
-  if (chosen) {
-    for (int st = 0; st < kTuneStages; ++st) chosen[st] = tuned_choice(*m, st, n);
-  }
   save_tuning(m);
+  return chosen ? nnp_get_variants(m, chosen) : NNP_OK;
+}
+
+nnp_status nnp_get_variants(nnp_model* m, int32_t* chosen) {
+  if (!m || !chosen) return set_error(NNP_EINVAL, "bad argument");
+  if (!m->reserved || m->last_n <= 0) return set_error(NNP_ESTATE, "nnp_get_variants needs a previous compute call");
+  chosen[kTuneNeighbours] = neighbour_variant(*m, m->last_n);
+  chosen[kTuneDescriptor] = descriptor_variant(*m, m->last_n);
+  chosen[kTuneNetwork] = mlp_variant(*m, m->last_n);
   return NNP_OK;
 }
 
@@ -778,6 +805,16 @@ nnp_status nnp_set_graph(nnp_model* m, int32_t enable) {
   if (!m) return set_error(NNP_EINVAL, "null model");
   m->graph_enabled = enable != 0;
   if (!m->graph_enabled) drop_graph(m);
+  return NNP_OK;
+}
+
+nnp_status nnp_set_variant(nnp_model* m, int32_t stage, int32_t variant) {
+  if (!m) return set_error(NNP_EINVAL, "null model");
+  if (stage < 0 || stage >= kTuneStages) return set_error(NNP_EINVAL, "unknown stage");
+  if (variant < -1 || variant >= kStageVariants[stage]) return set_error(NNP_EINVAL, "unknown variant");
+  HIP_TRY(hipDeviceSynchronize(), "nnp_set_variant");
+  drop_graph(m);
+  m->pinned[stage] = variant;
   return NNP_OK;
 }
 

@@ -523,6 +523,15 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// One wavefront per bin amortises the stencil set-up but needs enough bins
+// to fill the chip; with few bins (small boxes, one open system) work per
+// atom.  A pinned or tuned choice overrides the default.
+int neighbour_variant(const nnp_model& m, int n) {
+  if (m.geo.n_bins < 2) return 0;
+  const int v = stage_variant(m, kTuneNeighbours, n);
+  return v >= 0 ? v : (m.geo.n_bins >= 2048 ? 1 : 0);
+}
+
 hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   NeighArgs a;
@@ -542,14 +551,7 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   a.max_rad = m.max_rad;
   a.max_ang = m.max_ang;
   a.status = m.d_status;
-  // One wavefront per bin amortises the stencil set-up but needs enough bins
-  // to fill the chip; with few bins (small boxes, one open system) work per
-  // atom.  The autotuner may choose otherwise.
-  int v = m.force_variant[kTuneNeighbours] >= 0 ? m.force_variant[kTuneNeighbours]
-                                                 : tuned_choice(m, kTuneNeighbours, n);
-  if (v < 0) v = m.geo.n_bins >= 2048 ? 1 : 0;
-  if (m.geo.n_bins < 2) v = 0;
-  if (v == 1) {
+  if (neighbour_variant(m, n) == 1) {
     hipLaunchKernelGGL(k_neighbours_cell, dim3(m.geo.n_bins), dim3(64), 0, st, a, m.geo);
   } else {
     hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);

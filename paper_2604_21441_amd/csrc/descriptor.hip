@@ -265,6 +265,170 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row kernels: one 16-lane DPP row per atom, four atoms per wavefront.
+//
+// The lanes of a row split an output block's pairs (radial: strided over the
+// species segment; angular: a contiguous range of the class's (j, k) pairs),
+// each lane accumulating the whole block in registers; the row then sums the
+// block across its 16 lanes with a transposing butterfly (every step halves
+// the values a lane holds, so 16 values cost 15 exchanges and 32 cost 30),
+// leaving lane l with outputs [l B/16, (l+1) B/16).  The exchanges are DPP
+// row permutations: mirror (l <-> 15-l), half-mirror (l <-> 7-l within each
+// half) and the quad swaps xor 2 and xor 1; the pairings are disjoint, so
+// after four steps every lane's values cover all 16 lanes exactly once.
+
+constexpr int kRowAtoms = 16;        // atoms per 256-thread workgroup
+constexpr int kDppMirror = 0x140;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
+constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// v[0, 2H) -> v[0, H): keep the half selected by `upper`, add the partner's
+// copy of that half.
+template <int H, int CTRL>
+__device__ __forceinline__ void halve(float* v, bool upper) {
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const float keep = upper ? v[e + H] : v[e];
+    const float send = upper ? v[e] : v[e + H];
+    v[e] = keep + dpp<CTRL>(send);
+  }
+}
+
+// Sum N = 16 or 32 values over the 16 lanes of the row; lane `sub` ends with
+// totals [sub N/16, (sub+1) N/16) in v[0 .. N/16).
+template <int N>
+__device__ __forceinline__ void row_reduce(float* v, int sub) {
+  halve<N / 2, kDppMirror>(v, sub & 8);
+  halve<N / 4, kDppHalfMirror>(v, sub & 4);
+  halve<N / 8, kDppXor2>(v, sub & 2);
+  halve<N / 16, kDppXor1>(v, sub & 1);
+}
+
+// Start of a lane's contiguous range [r0, r1) of T unordered pairs within a
+// class, decoded to (j, k): same species: k-major over j < k; different
+// species: j-major over (j, k).
+__device__ __forceinline__ void pair_start(int r0, bool same, int nB, int* j, int* k) {
+  if (same) {
+    int kk = (int)((1.f + __builtin_amdgcn_sqrtf(1.f + 8.f * (float)r0)) * 0.5f);
+    if (kk * (kk - 1) / 2 > r0) --kk;      // the sqrt is within an ulp: one step each way
+    if ((kk + 1) * kk / 2 <= r0) ++kk;
+    *k = kk;
+    *j = r0 - kk * (kk - 1) / 2;
+  } else {
+    const int jj = (int)(((float)r0 + 0.5f) * __builtin_amdgcn_rcpf((float)max(nB, 1)));
+    *j = jj;
+    *k = r0 - jj * nB;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, Geometry geo) {
+  extern __shared__ float4 smem_r[];
+  const int row = threadIdx.x >> 4, sub = threadIdx.x & 15;
+  float4* G = smem_r + row * a.max_ang;                                      // (u, r hq)
+  float* W = reinterpret_cast<float*>(smem_r + kRowAtoms * a.max_ang) + row * a.max_ang;  // fc sq_pref
+  const int i = blockIdx.x * kRowAtoms + row;
+  const bool valid = i < a.n;
+  const Consts c = make_consts(p);
+  const int S1 = p.S + 1;
+  const int ii = valid ? i : 0;
+  const float4 pi = a.spos[ii];
+  const int* roff = a.rad_off + (int64_t)ii * S1;
+  const int* aoff = a.ang_off + (int64_t)ii * S1;
+  const int* rrow = a.rad + (int64_t)ii * a.max_rad;
+  const int* arow = a.ang + (int64_t)ii * a.max_ang;
+  float* xo = a.x + (int64_t)ii * p.stride;
+
+  // angular neighbour geometry of this row's atom
+  const int na = valid ? aoff[p.S] : 0;
+  for (int u = sub; u < na; u += 16) {
+    Geo d = displacement(pi, a.spos[arow[u]], geo);
+    G[u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
+    W[u] = (0.5f * cos_rev(d.r * c.inv2rca) + 0.5f) * p.sq_pref;
+  }
+
+  // radial blocks
+  for (int s = 0; s < p.S; ++s) {
+    float acc[kRadShifts];
+#pragma unroll
+    for (int k = 0; k < kRadShifts; ++k) acc[k] = 0.f;
+    const int t1 = valid ? roff[s + 1] : 0;
+    for (int t = (valid ? roff[s] : 0) + sub; t < t1; t += 16) {
+#pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
+      Geo d = displacement(pi, a.spos[rrow[t]], geo);
+      const float fc = fmaf(0.5f, cos_rev(d.r * c.inv2rc), 0.5f);
+      const float rs = d.r * p.sq_eta_r;
+#pragma unroll
+      for (int k = 0; k < kRadShifts; ++k) {
+        const float tt = rs - p.rad_shift_s[k];
+        acc[k] = fmaf(ex2(-(tt * tt)), fc, acc[k]);
+      }
+    }
+    row_reduce<kRadShifts>(acc, sub);
+    if (valid) xo[s * kRadShifts + sub] = acc[0];
+  }
+  __syncthreads();
+
+  // angular blocks
+  for (int q = 0; q < p.P; ++q) {
+    const int sa = p.pair_a[q], sb = p.pair_b[q];
+    const bool same = sa == sb;
+    int oa = 0, ob = 0, nA = 0, nB = 0;
+    if (valid) {
+      oa = aoff[sa];
+      nA = aoff[sa + 1] - oa;
+      ob = aoff[sb];
+      nB = aoff[sb + 1] - ob;
+    }
+    const int T = same ? nA * (nA - 1) / 2 : nA * nB;
+    const int r0 = (T * sub) >> 4, r1 = (T * (sub + 1)) >> 4;
+    float acc[kAngShifts * kAngSects];
+#pragma unroll
+    for (int e = 0; e < kAngShifts * kAngSects; ++e) acc[e] = 0.f;
+    if (r0 < r1) {
+      int j, k;
+      pair_start(r0, same, nB, &j, &k);
+      const int kbase = same ? oa : ob;
+      for (int r = r0; r < r1; ++r) {
+        const float4 gj = G[oa + j], gk = G[kbase + k];
+        const float F = W[oa + j] * W[kbase + k];
+        const float cs = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
+        const float ct = 0.95f * cs;
+        const float sn = __builtin_amdgcn_sqrtf(1.f - ct * ct);
+        const float rb = gj.w + gk.w;
+        float A[kAngSects];
+#pragma unroll
+        for (int n = 0; n < kAngSects; ++n) {
+          const float base = 1.f + ct * p.cos_sect[n] + sn * p.sin_sect[n];
+          A[n] = F * ex2(p.zeta * lg2(base));
+        }
+#pragma unroll
+        for (int m = 0; m < kAngShifts; ++m) {
+          const float tt = rb - p.ang_shift_s[m];
+          const float B = ex2(-(tt * tt));
+#pragma unroll
+          for (int n = 0; n < kAngSects; ++n) acc[m * kAngSects + n] = fmaf(B, A[n], acc[m * kAngSects + n]);
+        }
+        if (same) {
+          if (++j == k) { j = 0; ++k; }
+        } else {
+          if (++k == nB) { k = 0; ++j; }
+        }
+      }
+    }
+    row_reduce<kAngShifts * kAngSects>(acc, sub);
+    if (valid)
+      *reinterpret_cast<float2*>(xo + p.S * kRadShifts + q * kAngShifts * kAngSects + 2 * sub) =
+          make_float2(acc[0], acc[1]);
+  }
+}
+
 // Adjoint, one wavefront per centre atom i (no global atomics).
 //
 // E depends on d_ij = x_j - x_i, so a pair vector v = dE/d(d_ij) contributes
@@ -309,15 +473,9 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   double* sy = sx + a.max_rad;
   double* sz = sy + a.max_rad;
   float* gl = reinterpret_cast<float*>(sz + a.max_rad);   // [stride] dE/dx of the centre
-  float* gux = gl + p.stride;                    // angular neighbours, one array per component
-  float* guy = gux + a.max_ang;
-  float* guz = guy + a.max_ang;
-  float* gr = guz + a.max_ang;
-  float* gir = gr + a.max_ang;
-  float* gfc = gir + a.max_ang;
-  float* gdfc = gfc + a.max_ang;
-  int* gsp = reinterpret_cast<int*>(gdfc + a.max_ang);
-  int* rpos = gsp + a.max_ang;
+  // angular neighbours: (u, r hq) and (fc sq_pref, dfc sq_pref, 1/r, radial position * 8 + species)
+  float4* G1 = reinterpret_cast<float4*>(gl + p.stride + 2 * (a.max_rad & 1));   // 16-byte aligned
+  float4* G2 = G1 + a.max_ang;
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   const Consts c = make_consts(p);
@@ -327,7 +485,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   const int na = a.ang_off[(int64_t)i * S1 + p.S];
   const int* rrow = a.rad + (int64_t)i * a.max_rad;
   const int* arow = a.ang + (int64_t)i * a.max_ang;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
+  float fx = 0.f, fy = 0.f, fz = 0.f;   // this lane's share of the centre's total
 
   // 1. dE/dx row
   {
@@ -339,47 +497,46 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   for (int u = lane; u < na; u += 64) {
     const float4 pj = a.spos[arow[u]];
     Geo d = displacement(pi, pj, geo);
-    float arg = d.r * c.inv2rca;
-    gux[u] = d.dx * d.ir;
-    guy[u] = d.dy * d.ir;
-    guz[u] = d.dz * d.ir;
-    gr[u] = d.r;
-    gir[u] = d.ir;
-    gfc[u] = 0.5f * cos_rev(arg) + 0.5f;
-    gdfc[u] = c.dfc_a * sin_rev(arg);
-    gsp[u] = __float_as_int(pj.w);
-    rpos[u] = a.angpos[(int64_t)i * a.max_ang + u];
+    const float arg = d.r * c.inv2rca;
+    G1[u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
+    G2[u] = make_float4(fmaf(0.5f, cos_rev(arg), 0.5f) * p.sq_pref, c.dfc_a * sin_rev(arg) * p.sq_pref, d.ir,
+                        __int_as_float(a.angpos[(int64_t)i * a.max_ang + u] * 8 + __float_as_int(pj.w)));
   }
   __syncthreads();
   // 2. radial pairs
-  for (int t = lane; t < nr; t += 64) {
-    const float4 pj = a.spos[rrow[t]];
-    const int sj = __float_as_int(pj.w);
-    Geo d = displacement(pi, pj, geo);
-    float arg = d.r * c.inv2rc;
-    float fc = 0.5f * cos_rev(arg) + 0.5f;
-    float dfc = c.dfc_r * sin_rev(arg);
-    const float4* g4 = reinterpret_cast<const float4*>(gl + sj * kRadShifts);
-    float s0 = 0.f, s1 = 0.f;
+  {
+    const float c1 = -2.f * p.eta_rad / p.sq_eta_r;   // d/dr of -(r sq - Rs sq)^2 per (r sq - Rs sq), in ln units
+    for (int t = lane; t < nr; t += 64) {
+#pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
+      const float4 pj = a.spos[rrow[t]];
+      const int sj = __float_as_int(pj.w);
+      Geo d = displacement(pi, pj, geo);
+      const float arg = d.r * c.inv2rc;
+      const float fc = fmaf(0.5f, cos_rev(arg), 0.5f);
+      const float dfc = c.dfc_r * sin_rev(arg);
+      const float rs = d.r * p.sq_eta_r;
+      const float4* g4 = reinterpret_cast<const float4*>(gl + sj * kRadShifts);
+      float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-    for (int q = 0; q < kRadShifts / 4; ++q) {
-      float4 gv = g4[q];
-      float gk[4] = {gv.x, gv.y, gv.z, gv.w};
+      for (int q = 0; q < kRadShifts / 4; ++q) {
+        const float4 gv = g4[q];
+        const float gk[4] = {gv.x, gv.y, gv.z, gv.w};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        float tt = d.r - p.rad_shift[4 * q + u];
-        float B = gk[u] * ex2(-c.eta_r_l2 * tt * tt);
-        s0 += B;
-        s1 += B * tt;
+        for (int u = 0; u < 4; ++u) {
+          const float tt = rs - p.rad_shift_s[4 * q + u];
+          const float B = gk[u] * ex2(-(tt * tt));
+          s0 += B;
+          s1 = fmaf(B, tt, s1);
+        }
       }
+      const float dTdr = fmaf(dfc, s0, c1 * fc * s1);
+      const float w = dTdr * d.ir;
+      const float vx = w * d.dx, vy = w * d.dy, vz = w * d.dz;
+      sx[t] = vx;
+      sy[t] = vy;
+      sz[t] = vz;
+      fx += vx; fy += vy; fz += vz;
     }
-    float dTdr = dfc * s0 - 2.f * p.eta_rad * fc * s1;
-    float w = dTdr * d.ir;
-    float vx = w * d.dx, vy = w * d.dy, vz = w * d.dz;
-    sx[t] = vx;
-    sy[t] = vy;
-    sz[t] = vz;
-    fx += vx; fy += vy; fz += vz;
   }
   __syncthreads();
   // 4. angular triplets (j < k, k-major), a contiguous range per lane
@@ -387,78 +544,92 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   const int r0 = (int)(((int64_t)T * lane) >> 6);
   const int r1 = (int)(((int64_t)T * (lane + 1)) >> 6);
   if (r0 < r1) {
+#pragma clang fp contract(off)
     int k = (int)((1.f + __builtin_amdgcn_sqrtf(1.f + 8.f * (float)r0)) * 0.5f);
-    while (k * (k - 1) / 2 > r0) --k;
-    while ((k + 1) * k / 2 <= r0) ++k;
+    if (k * (k - 1) / 2 > r0) --k;
+    if ((k + 1) * k / 2 <= r0) ++k;
     int j = r0 - k * (k - 1) / 2;
-    double kx = 0.0, ky = 0.0, kz = 0.0;   // running total of the current k
+    const float c_sdr = -p.eta_ang / p.hq_eta_a;     // d rbar-term per (rbar sa - Ra sa), sa = 2 hq
+    const float c_dc = p.zeta * 0.95f;
+    float kx = 0.f, ky = 0.f, kz = 0.f;   // running total of the current k
+    float4 k1 = G1[k], k2 = G2[k];
     for (int r = r0; r < r1; ++r) {
-      const float ujx = gux[j], ujy = guy[j], ujz = guz[j], rj = gr[j], irj = gir[j], fcj = gfc[j], dfcj = gdfc[j];
-      const float ukx = gux[k], uky = guy[k], ukz = guz[k], rk = gr[k], irk = gir[k], fck = gfc[k], dfck = gdfc[k];
-      const int q = p.class_of[gsp[j]][gsp[k]];
+      const float4 j1 = G1[j], j2 = G2[j];
+      const int wj = __float_as_int(j2.w), wk = __float_as_int(k2.w);
+      const int sj = wj & 7, sk = wk & 7;                   // sj <= sk (rows are grouped by species)
+      const int q = sj * p.S - (sj * (sj - 1)) / 2 + (sk - sj);
       const float4* g4 = reinterpret_cast<const float4*>(gl + p.S * kRadShifts + q * kAngShifts * kAngSects);
-      float cs = ujx * ukx + ujy * uky + ujz * ukz;
-      float ct = 0.95f * cs;
-      float st = __builtin_amdgcn_sqrtf(1.f - ct * ct);
-      float ist = __builtin_amdgcn_rcpf(st);
-      float rbar = 0.5f * (rj + rk);
-      float A[kAngSects], dA[kAngSects];
+      const float cs = fmaf(j1.x, k1.x, fmaf(j1.y, k1.y, j1.z * k1.z));
+      const float ct = 0.95f * cs;
+      const float s2 = fmaf(-ct, ct, 1.f);
+      const float ist = rsq(s2);
+      const float st = s2 * ist;
+      const float qq = ct * ist;
+      const float rb = j1.w + k1.w;
+      float A[kAngSects], Ab[kAngSects];
 #pragma unroll
       for (int n = 0; n < kAngSects; ++n) {
-        float base = 1.f + ct * p.cos_sect[n] + st * p.sin_sect[n];
-        float An = ex2(p.zeta * lg2(base));
+        const float base = fmaf(st, p.sin_sect[n], fmaf(ct, p.cos_sect[n], 1.f));
+        const float An = ex2(p.zeta * lg2(base));
         A[n] = An;
-        dA[n] = p.zeta * An * __builtin_amdgcn_rcpf(base) * 0.95f * (p.cos_sect[n] - ct * ist * p.sin_sect[n]);
+        Ab[n] = An * __builtin_amdgcn_rcpf(base);
       }
       float h[kAngSects] = {0.f, 0.f, 0.f, 0.f};
       float sdr = 0.f;
 #pragma unroll
       for (int m = 0; m < kAngShifts; ++m) {
-        float4 gv = g4[m];
-        float G[4] = {gv.x, gv.y, gv.z, gv.w};
-        float tt = rbar - p.ang_shift[m];
-        float B = ex2(-c.eta_a_l2 * tt * tt);
-        float km = 0.f;
-#pragma unroll
-        for (int n = 0; n < kAngSects; ++n) {
-          h[n] += G[n] * B;
-          km += G[n] * A[n];
-        }
-        sdr += -2.f * p.eta_ang * tt * B * km;
+        const float4 gv = g4[m];
+        const float tt = rb - p.ang_shift_s[m];
+        const float B = ex2(-(tt * tt));
+        h[0] = fmaf(gv.x, B, h[0]);
+        h[1] = fmaf(gv.y, B, h[1]);
+        h[2] = fmaf(gv.z, B, h[2]);
+        h[3] = fmaf(gv.w, B, h[3]);
+        const float km = fmaf(gv.x, A[0], fmaf(gv.y, A[1], fmaf(gv.z, A[2], gv.w * A[3])));
+        sdr = fmaf(tt * B, km, sdr);
       }
-      float SA = 0.f, SdA = 0.f;
+      float SA = 0.f, SP = 0.f, SQ = 0.f;
 #pragma unroll
       for (int n = 0; n < kAngSects; ++n) {
-        SA += h[n] * A[n];
-        SdA += h[n] * dA[n];
+        SA = fmaf(h[n], A[n], SA);
+        const float wn = h[n] * Ab[n];
+        SP = fmaf(wn, p.cos_sect[n], SP);
+        SQ = fmaf(wn, p.sin_sect[n], SQ);
       }
-      float F = p.ang_pref * fcj * fck;
-      float dTdc = F * SdA;
-      float dTdrbar = F * sdr;
-      float dTdrj = 0.5f * dTdrbar + p.ang_pref * dfcj * fck * SA;
-      float dTdrk = 0.5f * dTdrbar + p.ang_pref * fcj * dfck * SA;
-      float cj = dTdc * irj, ck = dTdc * irk;
-      float vjx = cj * (ukx - cs * ujx) + dTdrj * ujx;
-      float vjy = cj * (uky - cs * ujy) + dTdrj * ujy;
-      float vjz = cj * (ukz - cs * ujz) + dTdrj * ujz;
-      float vkx = ck * (ujx - cs * ukx) + dTdrk * ukx;
-      float vky = ck * (ujy - cs * uky) + dTdrk * uky;
-      float vkz = ck * (ujz - cs * ukz) + dTdrk * ukz;
-      const int pj = rpos[j];
+      const float F = j2.x * k2.x;
+      const float dTdc = F * c_dc * fmaf(-qq, SQ, SP);
+      const float hdr = 0.5f * F * c_sdr * sdr;
+      const float dTdrj = fmaf(j2.y * k2.x, SA, hdr);
+      const float dTdrk = fmaf(j2.x * k2.y, SA, hdr);
+      const float cj = dTdc * j2.z, ck = dTdc * k2.z;
+      const float vjx = fmaf(cj, fmaf(-cs, j1.x, k1.x), dTdrj * j1.x);
+      const float vjy = fmaf(cj, fmaf(-cs, j1.y, k1.y), dTdrj * j1.y);
+      const float vjz = fmaf(cj, fmaf(-cs, j1.z, k1.z), dTdrj * j1.z);
+      const float vkx = fmaf(ck, fmaf(-cs, k1.x, j1.x), dTdrk * k1.x);
+      const float vky = fmaf(ck, fmaf(-cs, k1.y, j1.y), dTdrk * k1.y);
+      const float vkz = fmaf(ck, fmaf(-cs, k1.z, j1.z), dTdrk * k1.z);
+      const int pj = wj >> 3;
       unsafeAtomicAdd(sx + pj, (double)vjx);
       unsafeAtomicAdd(sy + pj, (double)vjy);
       unsafeAtomicAdd(sz + pj, (double)vjz);
       kx += vkx; ky += vky; kz += vkz;
-      fx += (double)vjx + (double)vkx;
-      fy += (double)vjy + (double)vky;
-      fz += (double)vjz + (double)vkz;
+      fx += vjx + vkx;
+      fy += vjy + vky;
+      fz += vjz + vkz;
       if (++j == k || r + 1 == r1) {   // k changes (or the range ends): flush its total
-        const int pk = rpos[k];
-        unsafeAtomicAdd(sx + pk, kx);
-        unsafeAtomicAdd(sy + pk, ky);
-        unsafeAtomicAdd(sz + pk, kz);
-        kx = ky = kz = 0.0;
-        if (j == k) { j = 0; ++k; }
+        const int pk = wk >> 3;
+        unsafeAtomicAdd(sx + pk, (double)kx);
+        unsafeAtomicAdd(sy + pk, (double)ky);
+        unsafeAtomicAdd(sz + pk, (double)kz);
+        kx = ky = kz = 0.f;
+        if (j == k) {
+          j = 0;
+          ++k;
+          if (r + 1 < r1) {
+            k1 = G1[k];
+            k2 = G2[k];
+          }
+        }
       }
     }
   }
@@ -477,24 +648,73 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
       a.contrib[(int64_t)j * a.max_rad + lo] = make_float4((float)-sx[t], (float)-sy[t], (float)-sz[t], 0.f);
   }
   // 6. the centre's own total
-  fx = wave_sum_d(fx);
-  fy = wave_sum_d(fy);
-  fz = wave_sum_d(fz);
+  double dx = wave_sum_d((double)fx), dy = wave_sum_d((double)fy), dz = wave_sum_d((double)fz);
   if (lane == 0) {
-    a.self[3 * (int64_t)i + 0] = fx;
-    a.self[3 * (int64_t)i + 1] = fy;
-    a.self[3 * (int64_t)i + 2] = fz;
+    a.self[3 * (int64_t)i + 0] = dx;
+    a.self[3 * (int64_t)i + 1] = dy;
+    a.self[3 * (int64_t)i + 2] = dz;
+  }
+}
+
+// FP64 energy reduction blocks, appended to the gather's grid (one launch for
+// both): with per-tile partials from the network kernel (a single system)
+// one block sums them; otherwise block `sys` sums that system's atomic
+// energies over its species buckets.  Fixed order, hence deterministic.
+struct EnergyArgs {
+  const double* part;      // per-tile partials, or null
+  const float* e;          // atomic energies in sorted order
+  const int* bin_start;    // species buckets [s * n_bins, (s + 1) * n_bins)
+  int n_bins, S, tile_rows;
+  int empty;               // no atoms: the energies are zero (the buckets are not read)
+  double* out;
+  int accumulate;
+  int* status;
+};
+
+__device__ __forceinline__ void energy_block(const EnergyArgs& ea, int sys) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  if (ea.empty) {
+  } else if (ea.part != nullptr) {
+    int tiles = 0;
+    for (int s = 0; s < ea.S; ++s)
+      tiles += (ea.bin_start[(s + 1) * ea.n_bins] - ea.bin_start[s * ea.n_bins] + ea.tile_rows - 1) / ea.tile_rows;
+    for (int t = threadIdx.x; t < tiles; t += kBlock) acc += ea.part[t];
+  } else {
+    for (int s = 0; s < ea.S; ++s) {
+      const int b0 = ea.bin_start[s * ea.n_bins + sys], b1 = ea.bin_start[s * ea.n_bins + sys + 1];
+      for (int t = b0 + threadIdx.x; t < b1; t += kBlock) acc += (double)ea.e[t];
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = red[0];
+    if (!isfinite(v)) atomicOr(ea.status, kStatusNonFinite);
+    ea.out[sys] = ea.accumulate ? ea.out[sys] + v : v;
   }
 }
 
 // F_atom += self + sum over the atom's radial list entries (FP64): 16 lanes
 // per atom, each summing a strided part of the row, then a shuffle tree.
+// With `assign` the sum overwrites F_atom (every row of the output is an NNP
+// atom and the call does not accumulate), which saves clearing it first.
+// Blocks from gather_blocks on reduce the energies instead.
 __global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ contrib,
                                                          const double* __restrict__ self,
                                                          const int* __restrict__ rad_off,
                                                          const int* __restrict__ slot_atom, int n, int S,
                                                          int max_rad, double* __restrict__ forces,
-                                                         double* __restrict__ link_forces) {
+                                                         double* __restrict__ link_forces, int assign,
+                                                         int gather_blocks, EnergyArgs ea) {
+  if ((int)blockIdx.x >= gather_blocks) {
+    energy_block(ea, (int)blockIdx.x - gather_blocks);
+    return;
+  }
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid >> 4;
   const int sub = gid & 15;
@@ -516,9 +736,17 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restric
   if (i < n && sub == 0) {
     const int a = slot_atom[i];   // a < 0: link atom -1 - a
     double* f = a >= 0 ? forces + 3 * (int64_t)a : link_forces + 3 * (int64_t)(-1 - a);
-    f[0] += fx + self[3 * (int64_t)i];
-    f[1] += fy + self[3 * (int64_t)i + 1];
-    f[2] += fz + self[3 * (int64_t)i + 2];
+    fx += self[3 * (int64_t)i];
+    fy += self[3 * (int64_t)i + 1];
+    fz += self[3 * (int64_t)i + 2];
+    if (!assign) {
+      fx += f[0];
+      fy += f[1];
+      fz += f[2];
+    }
+    f[0] = fx;
+    f[1] = fy;
+    f[2] = fz;
   }
 }
 
@@ -563,6 +791,13 @@ hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forc
   return hipGetLastError();
 }
 
+// Forward descriptor variants: 0 = one wavefront per atom, 1 = one 16-lane
+// row per atom (default).
+int descriptor_variant(const nnp_model& m, int n) {
+  const int v = stage_variant(m, kTuneDescriptor, n);
+  return v >= 0 ? v : 1;
+}
+
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   FwdArgs a;
@@ -575,8 +810,14 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   a.max_ang = m.max_ang;
   a.n = n;
   a.x = m.d_x;
-  size_t lds = sizeof(float) * (64 * (size_t)kPartStride + 5 * (size_t)m.max_ang);
-  hipLaunchKernelGGL(k_desc_fwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);
+  if (descriptor_variant(m, n) == 1) {
+    const size_t lds = (sizeof(float4) + sizeof(float)) * kRowAtoms * (size_t)m.max_ang;
+    hipLaunchKernelGGL(k_desc_fwd_rows, dim3((n + kRowAtoms - 1) / kRowAtoms), dim3(256), lds, st, a, m.dp,
+                       m.geo);
+  } else {
+    const size_t lds = sizeof(float) * (64 * (size_t)kPartStride + 5 * (size_t)m.max_ang);
+    hipLaunchKernelGGL(k_desc_fwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);
+  }
   return hipGetLastError();
 }
 
@@ -595,17 +836,32 @@ hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   a.g = m.d_g;
   a.contrib = m.d_contrib;
   a.self = m.d_self;
+  // FP64 slots, the dE/dx row, padding to 16 bytes, two float4 records per angular neighbour
   size_t lds = sizeof(double) * 3 * (size_t)m.max_rad + sizeof(float) * (size_t)m.stride +
-               sizeof(float) * 7 * (size_t)m.max_ang + sizeof(int) * 2 * (size_t)m.max_ang;
+               sizeof(float) * 2 * ((size_t)m.max_rad & 1) + sizeof(float4) * 2 * (size_t)m.max_ang;
   hipLaunchKernelGGL(k_desc_bwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);
   return hipGetLastError();
 }
 
-hipError_t launch_force_gather(nnp_model& m, int n, double* forces, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((16 * (int64_t)n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                     m.d_contrib, m.d_self,
-                     m.d_rad_off, m.d_slot_atom, n, m.S, m.max_rad, forces, m.d_link_F);
+hipError_t launch_force_gather(nnp_model& m, int n, double* forces, int assign, double* energies, int n_sys,
+                               int accumulate, hipStream_t st) {
+  EnergyArgs ea;
+  const bool single = m.geo.periodic || m.geo.n_bins == 1;
+  ea.part = single ? m.d_part : nullptr;
+  ea.e = m.d_e;
+  ea.bin_start = m.d_bin_start;
+  ea.n_bins = m.geo.n_bins;
+  ea.S = m.S;
+  ea.tile_rows = 16 * m.mlp_cols;
+  ea.empty = n == 0;
+  ea.out = energies;
+  ea.accumulate = accumulate;
+  ea.status = m.d_status;
+  const int gather_blocks = (int)((16 * (int64_t)n + kBlock - 1) / kBlock);
+  const int energy_blocks = single ? 1 : n_sys;
+  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)(gather_blocks + energy_blocks)), dim3(kBlock), 0, st,
+                     m.d_contrib, m.d_self, m.d_rad_off, m.d_slot_atom, n, m.S, m.max_rad, forces, m.d_link_F,
+                     assign, gather_blocks, ea);
   return hipGetLastError();
 }
 

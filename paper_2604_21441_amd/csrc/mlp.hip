@@ -571,60 +571,6 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reg(MlpArgs a, float alpha) {
   }
 }
 
-// Single-system energy: sum of the per-wavefront partials in a fixed order.
-constexpr int kFin = 256;
-__global__ __launch_bounds__(kFin) void k_energy_final(const double* __restrict__ part,
-                                                       const int* __restrict__ bin_start, int n_bins, int S,
-                                                       int tile_rows, double* __restrict__ out, int accumulate,
-                                                       int* __restrict__ status) {
-  __shared__ double red[kFin];
-  int tiles = 0;
-  for (int s = 0; s < S; ++s) tiles += (bin_start[(s + 1) * n_bins] - bin_start[s * n_bins] + tile_rows - 1) / tile_rows;
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < tiles; t += kFin) acc += part[t];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = kFin / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double v = red[0];
-    if (!isfinite(v)) atomicOr(status, kStatusNonFinite);
-    out[0] = accumulate ? out[0] + v : v;
-  }
-}
-
-// Per-system FP64 energy: a fixed-order block reduction (deterministic).
-constexpr int kRed = 256;
-__global__ __launch_bounds__(kRed) void k_energy(const float* __restrict__ e, const int* __restrict__ bin_start,
-                                                 int n_bins, int S, int single, double* __restrict__ out,
-                                                 int accumulate, int* __restrict__ status) {
-  __shared__ double part[kRed];
-  const int sys = blockIdx.x;
-  double acc = 0.0;
-  if (single) {
-    int n = bin_start[S * n_bins];
-    for (int t = threadIdx.x; t < n; t += kRed) acc += (double)e[t];
-  } else {
-    for (int s = 0; s < S; ++s) {
-      int b0 = bin_start[s * n_bins + sys], b1 = bin_start[s * n_bins + sys + 1];
-      for (int t = b0 + threadIdx.x; t < b1; t += kRed) acc += (double)e[t];
-    }
-  }
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = kRed / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double v = part[0];
-    if (!isfinite(v)) atomicOr(status, kStatusNonFinite);
-    out[sys] = accumulate ? out[sys] + v : v;
-  }
-}
-
 template <int K0, int N1, int N2, int N3, bool BF16>
 hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream_t st) {
   if (variant == 0) {        // register-resident, one wavefront per 16 atoms
@@ -650,7 +596,7 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
 // tuned choice for this size wins; otherwise BF16 products are short enough
 // for the register-resident kernel, and FP32 ones need the row split.
 int mlp_variant(const nnp_model& m, int n) {
-  int v = tuned_choice(m, kTuneNetwork, n);
+  int v = stage_variant(m, kTuneNetwork, n);
   if (v >= 0) return v;
   if (m.prec == NNP_BF16) return 0;
   return n >= 65536 ? 2 : 1;
@@ -674,7 +620,7 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.status = m.d_status;
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
-  const int v = m.force_variant[kTuneNetwork] >= 0 ? m.force_variant[kTuneNetwork] : mlp_variant(m, n);
+  const int v = mlp_variant(m, n);
   m.mlp_cols = v == 2 ? 2 : 1;
   switch (m.net_kind) {
     case 0:
@@ -686,17 +632,6 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
     default:
       return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st) {
-  if (m.geo.periodic || m.geo.n_bins == 1) {
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kFin), 0, st, m.d_part, m.d_bin_start, m.geo.n_bins, m.S,
-                       16 * m.mlp_cols, energies, accumulate, m.d_status);
-  } else {
-    hipLaunchKernelGGL(k_energy, dim3(n_sys), dim3(kRed), 0, st, m.d_e, m.d_bin_start, m.geo.n_bins, m.S, 0,
-                       energies, accumulate, m.d_status);
-  }
-  return hipGetLastError();
 }
 
 }  // namespace nnp

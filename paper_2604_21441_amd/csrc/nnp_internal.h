@@ -36,6 +36,11 @@ struct DescParams {
   float rad_shift[kRadShifts];
   float ang_shift[kAngShifts];
   float cos_sect[kAngSects], sin_sect[kAngSects];
+  // Pre-scaled forms used by the row kernels: exp(-eta (r - Rs)^2) =
+  // exp2(-(r sq - Rs sq)^2) with sq = sqrt(eta log2 e); the angular mean
+  // distance enters as r_j hq + r_k hq with hq = sq / 2; sq_pref^2 = 2^(1-zeta).
+  float sq_eta_r, hq_eta_a, sq_pref;
+  float rad_shift_s[kRadShifts], ang_shift_s[kAngShifts];
   float mm_cutoff, ke;
   int S, P, D, stride;                  // species, pair classes, descriptor length, row stride
   int extra;                            // 1 if the MM potential is the last input
@@ -98,6 +103,7 @@ struct nnp_model {
   int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
   std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
   int force_variant[nnp::kTuneStages] = {-1, -1, -1};   // set while timing candidates
+  int pinned[nnp::kTuneStages] = {-1, -1, -1};          // nnp_set_variant
   int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
   std::vector<float> w_host;            // canonical FP32 weights, draw order
 
@@ -176,6 +182,13 @@ namespace nnp {
 
 // autotuner (api.cpp): tuned variant of a stage for n atoms, or -1
 int tuned_choice(const nnp_model& m, int stage, int n);
+int descriptor_variant(const nnp_model& m, int n);
+int neighbour_variant(const nnp_model& m, int n);
+int mlp_variant(const nnp_model& m, int n);
+// Variant of a tuned stage: the candidate being timed, else the pinned one,
+// else the tuned choice for this size; -1 means the stage's default.
+int stage_variant(const nnp_model& m, int stage, int n);
+constexpr int kStageVariants[kTuneStages] = {2, 2, 3};
 int size_bucket(int n);
 
 // error helpers (api.cpp)
@@ -195,7 +208,8 @@ hipError_t launch_neighbours(nnp_model& m, int n_nnp, hipStream_t st);
 // descriptor.hip
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st);
 hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st);
-hipError_t launch_force_gather(nnp_model& m, int n, double* forces, hipStream_t st);
+hipError_t launch_force_gather(nnp_model& m, int n, double* forces, int assign, double* energies, int n_sys,
+                               int accumulate, hipStream_t st);
 
 // mm.hip
 hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
@@ -205,7 +219,6 @@ hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, con
 
 // mlp.hip
 hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st);
-hipError_t launch_energy(nnp_model& m, int n_sys, double* energies, int accumulate, hipStream_t st);
 
 // fills (api.cpp)
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t st);

@@ -18,7 +18,7 @@ from . import _lib as L
 
 __all__ = [
     "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
-    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_variant", "nnp_get_variants", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
 
@@ -169,6 +169,22 @@ def nnp_autotune(h, reps: int = 5, stream=None) -> dict:
     return {"neighbours": chosen[0], "descriptor": chosen[1], "network": chosen[2]}
 
 
+TUNE_STAGES = {"neighbours": 0, "descriptor": 1, "network": 2}
+
+
+def nnp_get_variants(h) -> dict:
+    """Kernel variants a call of the previous call's size and geometry runs."""
+    chosen = (C.c_int32 * 3)()
+    _check(L.load().nnp_get_variants(h, chosen), "nnp_get_variants")
+    return {k: chosen[v] for k, v in TUNE_STAGES.items()}
+
+
+def nnp_set_variant(h, stage, variant: int) -> None:
+    """Pin a stage's kernel variant (-1: tuned choice / default); stage by name or number."""
+    st = TUNE_STAGES[stage] if isinstance(stage, str) else int(stage)
+    _check(L.load().nnp_set_variant(h, st, int(variant)), "nnp_set_variant")
+
+
 def nnp_set_links(h, ml_idx, mm_idx, distance: float = 1.0, link_Z: int = 1) -> None:
     """Link atoms on the bonds ml_idx[l] (inside the index group) -> mm_idx[l] (outside), eq. 4."""
     ml, mlp = _host(ml_idx, np.int32, "ml_idx")
@@ -260,6 +276,12 @@ class NNPModel:
 
     def autotune(self, reps: int = 5) -> dict:
         return nnp_autotune(self.h, reps)
+
+    def set_variant(self, stage, variant: int) -> None:
+        nnp_set_variant(self.h, stage, variant)
+
+    def variants(self) -> dict:
+        return nnp_get_variants(self.h)
 
     def status(self, stream=None) -> int:
         return nnp_get_status(self.h, stream)
