@@ -216,7 +216,10 @@ typedef enum {
   NNP_BUF_DESCRIPTOR = 6, /* float [n_nnp][row stride] per sorted slot           */
   NNP_BUF_ATOM_ENERGY = 7,/* float [n_nnp] atomic energies per sorted slot        */
   NNP_BUF_DEDX = 8,       /* float [n_nnp][row stride] dE/d(descriptor) per slot  */
-  NNP_BUF_GRID = 9        /* int32 [4]: n_bins, cells per dimension x, y, z      */
+  NNP_BUF_GRID = 9,       /* int32 [4]: n_bins, cells per dimension x, y, z      */
+  NNP_BUF_ORDER = 10      /* int32 [n_nnp]: slots in the order the per-atom
+                             kernels visit them: bin by bin, species by species
+                             within a bin, ascending slot within a species     */
 } nnp_buffer;
 
 /*
@@ -230,15 +233,19 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
 /*
  * Autotuner.  Several stages have more than one kernel variant (network:
  * register-resident wavefronts or row-split workgroups of 16 or 32 atoms;
- * neighbour search: one wavefront per atom or per cell).  nnp_autotune times
- * each candidate `reps` times on the workspace of the previous compute call
- * (same size and geometry) and keeps the fastest for that size bucket
- * (quarter octaves of the atom count); later calls of that size use it.
- * chosen (host, [3] or NULL) receives the variants now used for the
- * neighbour, descriptor and network stages, as nnp_get_variants.
- * Synchronises the stream; drops the cached graph.  If the environment
- * variable NNP_TUNE_CACHE names a file, results are appended to it and
- * read back by nnp_create for the same GPU architecture and model shape.
+ * descriptor forward: a wavefront or a 16-lane row per atom; neighbour
+ * search: one wavefront per atom or per cell).  nnp_autotune reruns the
+ * stages after the cell list `reps` times (1..256) per candidate on the
+ * workspace of the previous compute call (same size and geometry; the
+ * caller's buffers are neither read nor written), times the stage being
+ * tuned with events in that context, and keeps the fastest for that size
+ * bucket (quarter octaves of the atom count); later calls of that size use
+ * it.  Pinned stages (nnp_set_variant) are skipped.  chosen (host, [3] or
+ * NULL) receives the variants now used for the neighbour, descriptor and
+ * network stages, as nnp_get_variants.  Synchronises the stream; drops the
+ * cached graph.  If the environment variable NNP_TUNE_CACHE names a file,
+ * results are appended to it and read back by nnp_create for the same GPU
+ * architecture and model shape.
  */
 nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t stream);
 

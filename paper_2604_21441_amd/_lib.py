@@ -36,6 +36,7 @@ NNP_BUF_DESCRIPTOR = 6
 NNP_BUF_ATOM_ENERGY = 7
 NNP_BUF_DEDX = 8
 NNP_BUF_GRID = 9
+NNP_BUF_ORDER = 10
 
 # nnp_stage
 STAGES = ["cells", "neighbours", "descriptor", "mm", "network", "energy", "adjoint", "gather", "mm_adjoint"]

@@ -124,7 +124,7 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
 
 void free_workspace(nnp_model* m) {
   dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_sys_off); dfree(m->d_key); dfree(m->d_bin_count);
-  dfree(m->d_bin_start); dfree(m->d_cursor); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
+  dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
   dfree(m->d_slot_atom); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
   dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
@@ -365,8 +365,9 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_slot_atom, n));
   chk(dalloc(&m->d_spos, n));
   chk(dalloc(&m->d_bin_count, (size_t)m->max_bins));
-  chk(dalloc(&m->d_cursor, (size_t)m->max_bins));
   chk(dalloc(&m->d_bin_start, (size_t)m->max_bins + 1));
+  chk(dalloc(&m->d_cmstart, (size_t)m->max_bins));
+  chk(dalloc(&m->d_order, n));
   chk(dalloc(&m->d_nbr_rad, n * m->max_rad));
   chk(dalloc(&m->d_nbr_ang, n * m->max_ang));
   chk(dalloc(&m->d_rad_off, n * (m->S + 1)));
@@ -667,6 +668,7 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
   switch (which) {
     case NNP_BUF_PERM: src = m->d_perm; count = n; break;
     case NNP_BUF_KEY: src = m->d_key; count = n; break;
+    case NNP_BUF_ORDER: src = m->d_order; count = n; break;
     case NNP_BUF_BIN_START: src = m->d_bin_start; count = (int64_t)m->S * m->geo.n_bins + 1; break;
     case NNP_BUF_NBR_RAD: src = m->d_nbr_rad; count = (int64_t)n * m->max_rad; stride = m->max_rad; break;
     case NNP_BUF_NBR_ANG: src = m->d_nbr_ang; count = (int64_t)n * m->max_ang; stride = m->max_ang; break;
@@ -710,30 +712,54 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
 }
 
 nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t stream) {
-  if (!m || reps < 1) return set_error(NNP_EINVAL, "bad argument");
+  if (!m || reps < 1 || reps > 256) return set_error(NNP_EINVAL, "bad argument");
   if (!m->reserved || m->last_n <= 0) return set_error(NNP_ESTATE, "nnp_autotune needs a previous compute call");
   HIP_TRY(hipStreamSynchronize(stream), "nnp_autotune");
   drop_graph(m);
   const int n = m->last_n;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0), "nnp_autotune");
-  HIP_TRY(hipEventCreate(&e1), "nnp_autotune");
+  // Each candidate is timed in context: the stages after the cell list run in
+  // their usual order on the previous call's workspace (positions already
+  // sorted; nothing of the caller's is read or written), with events around
+  // the stage being tuned only.
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  auto destroy = [&]() {
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+  };
+  if (e != hipSuccess) {
+    destroy();
+    return hip_error(e, "nnp_autotune");
+  }
+  auto pass = [&](int stage, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
+    hipError_t r = hipSuccess;
+    auto timed = [&](int st_id, auto&& launch) {
+      if (r != hipSuccess) return;
+      if (st_id == stage && e0) r = hipEventRecord(e0, stream);
+      if (r == hipSuccess) r = launch();
+      if (r == hipSuccess && st_id == stage && e1) r = hipEventRecord(e1, stream);
+    };
+    timed(kTuneNeighbours, [&] { return launch_neighbours(*m, n, stream); });
+    timed(kTuneDescriptor, [&] { return launch_descriptor_fwd(*m, n, stream); });
+    timed(kTuneNetwork, [&] { return launch_mlp(*m, n, stream); });
+    timed(-1, [&] { return launch_descriptor_bwd(*m, n, stream); });
+    return r;
+  };
   auto time_stage = [&](int stage, int v, float* ms) -> nnp_status {
     m->force_variant[stage] = v;
-    hipError_t e = hipSuccess;
-    auto run = [&]() {
-      return stage == kTuneNetwork      ? launch_mlp(*m, n, stream)
-             : stage == kTuneDescriptor ? launch_descriptor_fwd(*m, n, stream)
-                                        : launch_neighbours(*m, n, stream);
-    };
-    e = run();  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    hipError_t r = pass(stage, nullptr, nullptr);   // warm-up
+    for (int k = 0; k < reps && r == hipSuccess; ++k) r = pass(stage, ev[2 * k], ev[2 * k + 1]);
+    if (r == hipSuccess) r = hipStreamSynchronize(stream);
+    *ms = 0.f;
+    for (int k = 0; k < reps && r == hipSuccess; ++k) {
+      float t = 0.f;
+      r = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+      *ms += t;
+    }
     m->force_variant[stage] = -1;
-    return e == hipSuccess ? NNP_OK : hip_error(e, "nnp_autotune");
+    return r == hipSuccess ? NNP_OK : hip_error(r, "nnp_autotune");
   };
   const int stages[3] = {kTuneNetwork, kTuneDescriptor, kTuneNeighbours};
   nnp_status status = NNP_OK;
@@ -753,8 +779,7 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
     if (status != NNP_OK) break;
     m->tuned[{st, size_bucket(n)}] = best;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  destroy();
   if (status != NNP_OK) return status;
   save_tuning(m);
   return chosen ? nnp_get_variants(m, chosen) : NNP_OK;

@@ -80,70 +80,164 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
   atomicAdd(&bin_count[k], 1);
 }
 
-// Exclusive scan of the bin histogram by one workgroup; also seeds the
-// scatter cursors and clears the histogram for the next call (it is zeroed
-// once when the workspace is reserved).
+// Exclusive scans of the bin histogram by one workgroup.
+//   start: species-major order (key = species * n_bins + bin), the slot
+//     order of the sorted arrays;
+//   cmstart[bin * S + species]: bin-major order, the order in which the
+//     per-atom kernels visit the slots (all species of a cell or system
+//     together, so neighbouring atoms are processed close in time).
+// Chunks of kScanChunk entries are staged through LDS so that every global
+// load and store is coalesced (per-thread runs of consecutive entries read
+// straight from memory are several times slower); each thread scans
+// kScanPer consecutive entries of the staged chunk.  The histogram itself is
+// left as it is: the scatter takes its cursors from it.
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(int* __restrict__ count,
-                                                       int* __restrict__ start,
-                                                       int* __restrict__ cursor, int n) {
-  __shared__ int part[kScanThreads];
-  int tid = threadIdx.x;
-  int per = (n + kScanThreads - 1) / kScanThreads;
-  int lo = tid * per;
-  int hi = min(n, lo + per);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += count[i];
-  part[tid] = s;
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+__device__ __forceinline__ int scan_pad(int i) { return i + i / kScanPer; }   // LDS bank spread
+
+// Exclusive prefix of v over the workgroup (thread order); *total receives the sum.
+__device__ __forceinline__ int block_exclusive(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the per-thread totals
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  if (wave == 0) {
+    const int w = lane < kScanThreads / 64 ? wsum[lane] : 0;
+    int wi = w;
+#pragma unroll
+    for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+      const int u = __shfl_up(wi, off, 64);
+      if (lane >= off) wi += u;
+    }
+    if (lane < kScanThreads / 64) wsum[kScanThreads / 64 + lane] = wi - w;
+    if (lane == kScanThreads / 64 - 1) wsum[2 * (kScanThreads / 64)] = wi;
   }
-  int run = tid == 0 ? 0 : part[tid - 1];
-  for (int i = lo; i < hi; ++i) {
-    const int c = count[i];
-    start[i] = run;
-    cursor[i] = run;
-    run += c;
-    count[i] = 0;   // the histogram starts from zero in the next call
-  }
-  if (tid == kScanThreads - 1) start[n] = part[kScanThreads - 1];
+  __syncthreads();
+  const int ex = wsum[kScanThreads / 64 + wave] + inc - v;
+  *total = wsum[2 * (kScanThreads / 64)];
+  __syncthreads();   // wsum is reused by the next call
+  return ex;
 }
 
+// Scan of the staged chunk buf[0 .. kScanChunk) in place (exclusive, plus carry).
+__device__ __forceinline__ void scan_chunk(int* buf, int* wsum, int* carry) {
+  int v[kScanPer];
+  int sum = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    v[u] = buf[scan_pad(threadIdx.x * kScanPer + u)];
+    sum += v[u];
+  }
+  int total;
+  int run = block_exclusive(sum, wsum, &total) + *carry;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    buf[scan_pad(threadIdx.x * kScanPer + u)] = run;
+    run += v[u];
+  }
+  *carry += total;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ count, int* __restrict__ start,
+                                                       int* __restrict__ cmstart, int S, int n_bins) {
+  __shared__ int wsum[2 * (kScanThreads / 64) + 1];
+  __shared__ int buf[kScanChunk + kScanChunk / kScanPer];
+  const int nb = S * n_bins;
+  int carry = 0;
+  // bin-major: bin b carries T[b], the sum of its species counts
+  for (int c0 = 0; c0 < n_bins; c0 += kScanChunk) {
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
+      int t = 0;
+#pragma unroll
+      for (int s = 0; s < kMaxSpecies; ++s)
+        if (s < S && b < n_bins) t += count[s * n_bins + b];
+      buf[scan_pad(i)] = t;
+    }
+    __syncthreads();
+    scan_chunk(buf, wsum, &carry);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
+      if (b < n_bins) {
+        int r = buf[scan_pad(i)];
+#pragma unroll
+        for (int s = 0; s < kMaxSpecies; ++s)
+          if (s < S) {
+            cmstart[b * S + s] = r;
+            r += count[s * n_bins + b];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // species-major
+  carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x;
+      buf[scan_pad(i)] = c0 + i < nb ? count[c0 + i] : 0;
+    }
+    __syncthreads();
+    scan_chunk(buf, wsum, &carry);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x;
+      if (c0 + i < nb) start[c0 + i] = buf[scan_pad(i)];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) start[nb] = carry;
+}
+
+// Provisional slots: start of the key plus an atomically drawn place (the
+// histogram counts down to zero, which also clears it for the next call).
 __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key, int n,
-                                                    int* __restrict__ cursor,
+                                                    const int* __restrict__ start, int* __restrict__ count,
                                                     int* __restrict__ tmp) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  int slot = atomicAdd(&cursor[key[t]], 1);
-  tmp[slot] = t;
+  const int k = key[t];
+  tmp[start[k] + atomicSub(&count[k], 1) - 1] = t;
 }
 
 // One wavefront per bin: the atomically scattered entries of the bin are
 // ranked by atom index (a stable order independent of the atomic order), and
-// the sorted positions / species / atom indices are written per slot.
+// the sorted positions / species / atom indices are written per slot, and
+// each slot's place in the bin-major visiting order.
 __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ start, int n_bins_total,
                                                     const int* __restrict__ tmp,
                                                     const float* __restrict__ pos,
                                                     const int* __restrict__ idx,
                                                     const int* __restrict__ sigma, Geometry g, LinkArgs L,
+                                                    const int* __restrict__ cmstart, int S,
                                                     int* __restrict__ perm,
                                                     float4* __restrict__ spos,
-                                                    int* __restrict__ slot_atom) {
+                                                    int* __restrict__ slot_atom,
+                                                    int* __restrict__ order) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= n_bins_total) return;
   int b0 = start[wave], b1 = start[wave + 1];
+  const int sp = wave / g.n_bins, bin = wave - sp * g.n_bins;
+  const int o0 = cmstart[bin * S + sp];
   for (int e = b0 + lane; e < b1; e += 64) {
     int t = tmp[e];
     int rank = 0;
     for (int q = b0; q < b1; ++q) rank += tmp[q] < t;
     int slot = b0 + rank;
     perm[slot] = t;
+    order[o0 + rank] = slot;
     const int a = idx[t];
     const float3 p = nnp_position(pos, a, L, g);
     spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sigma[t]));
@@ -160,11 +254,13 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
                                                       const int* __restrict__ bin_start,
                                                       const int* __restrict__ sigma,
                                                       const int* __restrict__ idx, const float* __restrict__ pos,
-                                                      Geometry g, LinkArgs L,
+                                                      Geometry g, LinkArgs L, const int* __restrict__ cmstart,
                                                       int* __restrict__ perm, float4* __restrict__ spos,
-                                                      int* __restrict__ slot_atom) {
+                                                      int* __restrict__ slot_atom, int* __restrict__ order,
+                                                      int* __restrict__ count) {
   const int m = blockIdx.x;
   const int lane = threadIdx.x;
+  if (lane < S) count[lane * n_sys + m] = 0;   // the histogram starts from zero in the next call
   const int t0 = sys_off[m], t1 = sys_off[m + 1];
   const uint64_t lt = __lanemask_lt();
   int base[kMaxSpecies] = {0, 0, 0, 0};
@@ -172,18 +268,22 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
     const int t = c0 + lane;
     const bool ok = t < t1;
     const int sg = ok ? sigma[t] : -1;
-    int slot = 0;
+    int slot = 0, rank = 0;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
       if (s < S) {
         const uint64_t mk = __ballot(sg == s);
-        if (sg == s) slot = bin_start[s * n_sys + m] + base[s] + __popcll(mk & lt);
+        if (sg == s) {
+          rank = base[s] + __popcll(mk & lt);
+          slot = bin_start[s * n_sys + m] + rank;
+        }
         base[s] += __popcll(mk);
       }
     }
     if (ok) {
       const int a = idx[t];
       perm[slot] = t;
+      order[cmstart[m * S + sg] + rank] = slot;
       const float3 p = nnp_position(pos, a, L, g);
       spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sg));
       slot_atom[slot] = a;
@@ -192,6 +292,7 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
 }
 
 struct NeighArgs {
+  const int* order;        // bin-major visiting order of the slots
   const float4* spos;
   const int* perm;
   const int* key;
@@ -221,7 +322,7 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   __shared__ int s_cell[kMaxStencil];
   __shared__ int s_start[kMaxStencil];
   __shared__ int s_off[kMaxStencil];
-  const int i = blockIdx.x;
+  const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const float4 pi = a.spos[i];
   const int bin = a.key[a.perm[i]] % g.n_bins;
@@ -354,7 +455,7 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g)
   __shared__ int s_off[kMaxStencil];
   __shared__ float4 s_cpos[64];
   __shared__ int s_cid[64];
-  const int cell = blockIdx.x;
+  const int cell = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   int nst = 1;
   int my_cell = -1;
@@ -507,18 +608,19 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
                        m.d_sigma, m.d_sys, g, L, m.d_key, m.d_bin_count, m.d_status);
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start,
-                     m.d_cursor, nb);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
+                     m.S, g.n_bins);
   if (n > 0 && !g.periodic) {
     hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
-                       m.d_sigma, m.d_idx, pos, g, L, m.d_perm, m.d_spos, m.d_slot_atom);
+                       m.d_sigma, m.d_idx, pos, g, L, m.d_cmstart, m.d_perm, m.d_spos, m.d_slot_atom,
+                       m.d_order, m.d_bin_count);
   } else if (n > 0) {
     int* tmp = m.d_tmp;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
-                       m.d_cursor, tmp);
+                       m.d_bin_start, m.d_bin_count, tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
-                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_perm, m.d_spos,
-                       m.d_slot_atom);
+                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
+                       m.d_spos, m.d_slot_atom, m.d_order);
   }
   return hipGetLastError();
 }
@@ -535,6 +637,7 @@ int neighbour_variant(const nnp_model& m, int n) {
 hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   NeighArgs a;
+  a.order = m.d_order;
   a.spos = m.d_spos;
   a.perm = m.d_perm;
   a.key = m.d_key;

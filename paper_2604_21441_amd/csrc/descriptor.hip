@@ -117,6 +117,7 @@ __device__ __forceinline__ void split_lanes(const int* cnt, int nb, int lane, in
 // divisions, and accumulates the 32 terms in registers.  Each phase ends
 // with a fixed-order reduction of the per-lane partial sums through LDS.
 struct FwdArgs {
+  const int* order;        // bin-major visiting order of the slots
   const float4* spos;
   const int* rad;
   const int* ang;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
   float* guz = guy + a.max_ang;
   float* gr = guz + a.max_ang;
   float* gfc = gr + a.max_ang;
-  const int i = blockIdx.x;
+  const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
@@ -333,11 +334,11 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
   const int row = threadIdx.x >> 4, sub = threadIdx.x & 15;
   float4* G = smem_r + row * a.max_ang;                                      // (u, r hq)
   float* W = reinterpret_cast<float*>(smem_r + kRowAtoms * a.max_ang) + row * a.max_ang;  // fc sq_pref
-  const int i = blockIdx.x * kRowAtoms + row;
-  const bool valid = i < a.n;
+  const int li = xcd_block(blockIdx.x, gridDim.x) * kRowAtoms + row;   // place in the visiting order
+  const bool valid = li < a.n;
   const Consts c = make_consts(p);
   const int S1 = p.S + 1;
-  const int ii = valid ? i : 0;
+  const int ii = valid ? a.order[li] : 0;
   const float4 pi = a.spos[ii];
   const int* roff = a.rad_off + (int64_t)ii * S1;
   const int* aoff = a.ang_off + (int64_t)ii * S1;
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
 // k_force_gather then sums, per atom and in FP64, its own total and the
 // entries of its list, and adds the result to the caller's force array.
 struct BwdArgs {
+  const int* order;        // bin-major visiting order of the slots
   const float4* spos;
   const int* rad;
   const int* ang;
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   // angular neighbours: (u, r hq) and (fc sq_pref, dfc sq_pref, 1/r, radial position * 8 + species)
   float4* G1 = reinterpret_cast<float4*>(gl + p.stride + 2 * (a.max_rad & 1));   // 16-byte aligned
   float4* G2 = G1 + a.max_ang;
-  const int i = blockIdx.x;
+  const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
@@ -801,6 +803,7 @@ int descriptor_variant(const nnp_model& m, int n) {
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   FwdArgs a;
+  a.order = m.d_order;
   a.spos = m.d_spos;
   a.rad = m.d_nbr_rad;
   a.ang = m.d_nbr_ang;
@@ -824,6 +827,7 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
 hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   BwdArgs a;
+  a.order = m.d_order;
   a.spos = m.d_spos;
   a.rad = m.d_nbr_rad;
   a.ang = m.d_nbr_ang;

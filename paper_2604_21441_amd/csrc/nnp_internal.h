@@ -24,6 +24,17 @@ constexpr int kTileAtoms = 16;   // atoms per wavefront in the network kernels
 // Stages with several kernel variants chosen by the autotuner.
 enum TuneStage { kTuneNeighbours = 0, kTuneDescriptor = 1, kTuneNetwork = 2, kTuneStages = 3 };
 
+// Workgroups are dispatched round-robin over the XCDs, each with its own L2.
+// xcd_block renumbers them so that every XCD works through one contiguous
+// range of the visiting order (a bijection of [0, G)); correctness never
+// depends on it.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // Device status bits.
 constexpr int kStatusCapacity = 1;
 constexpr int kStatusNonFinite = 2;
@@ -124,7 +135,8 @@ struct nnp_model {
   int* d_key = nullptr;
   int* d_bin_count = nullptr;
   int* d_bin_start = nullptr;  // [max_bins + 1]
-  int* d_cursor = nullptr;
+  int* d_cmstart = nullptr;    // [max_bins] bin-major starts (bin * S + species)
+  int* d_order = nullptr;      // [max_atoms] slots in bin-major visiting order
   int* d_perm = nullptr;       // slot -> NNP-local atom
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
   float4* d_spos = nullptr;    // slot -> position (w = species bits)

@@ -56,14 +56,17 @@ def water_models(P, w_water):
 
 @pytest.fixture(scope="module")
 def boxes():
-    return {"c1": sy.water_box(64, 12.42, seed=0), "c2": sy.water_box(4096, 49.7, seed=0)}
+    # "large" (18,432 atoms) adds a box of several scan chunks per species
+    return {"c1": sy.water_box(64, 12.42, seed=0), "c2": sy.water_box(4096, 49.7, seed=0),
+            "large": sy.water_box(6144, 56.9, seed=0)}
 
 
 @pytest.fixture(scope="module")
 def oracle_res(boxes, w_water):
     out = {}
     for k, (pos, Z, box) in boxes.items():
-        out[k] = orc.evaluate(pos, Z, WATER, w_water, box=box, return_x=True)
+        if k != "large":
+            out[k] = orc.evaluate(pos, Z, WATER, w_water, box=box, return_x=True)
     return out
 
 
@@ -76,7 +79,7 @@ def _run(model, pos, Z, box, **kw):
 
 
 # ------------------------------------------------------------ integer stages
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "large"])
 def test_cell_list_bit_exact(P, water_models, boxes, name):
     pos, Z, box = boxes[name]
     m = water_models["fp32"]
@@ -88,6 +91,10 @@ def test_cell_list_bit_exact(P, water_models, boxes, name):
     assert np.array_equal(m.read(P._lib.NNP_BUF_KEY), ref["key"])
     assert np.array_equal(m.read(P._lib.NNP_BUF_PERM), ref["perm"])
     assert np.array_equal(m.read(P._lib.NNP_BUF_BIN_START), ref["bin_start"])
+    # visiting order: bin by bin, species by species, ascending slot
+    bs, nb = ref["bin_start"], len(ref["bin_start"]) // 2
+    expect = np.concatenate([np.arange(bs[s * nb + b], bs[s * nb + b + 1]) for b in range(nb) for s in range(2)])
+    assert np.array_equal(m.read(P._lib.NNP_BUF_ORDER), expect)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
