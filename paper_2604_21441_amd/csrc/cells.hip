@@ -150,8 +150,52 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ c
                                                        int* __restrict__ cmstart, int S, int n_bins) {
   __shared__ int wsum[2 * (kScanThreads / 64) + 1];
   __shared__ int buf[kScanChunk + kScanChunk / kScanPer];
+  __shared__ int bufc[kScanChunk + kScanChunk / kScanPer];
   const int nb = S * n_bins;
   int carry = 0;
+  if (nb <= kScanChunk) {
+    // one chunk: the histogram is read once and both scans run from LDS
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x;
+      bufc[scan_pad(i)] = i < nb ? count[i] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int b = u * kScanThreads + threadIdx.x;
+      int t = 0;
+#pragma unroll
+      for (int s = 0; s < kMaxSpecies; ++s)
+        if (s < S && b < n_bins) t += bufc[scan_pad(s * n_bins + b)];
+      buf[scan_pad(b)] = t;
+    }
+    __syncthreads();
+    scan_chunk(buf, wsum, &carry);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int b = u * kScanThreads + threadIdx.x;
+      if (b < n_bins) {
+        int r = buf[scan_pad(b)];
+#pragma unroll
+        for (int s = 0; s < kMaxSpecies; ++s)
+          if (s < S) {
+            cmstart[b * S + s] = r;
+            r += bufc[scan_pad(s * n_bins + b)];
+          }
+      }
+    }
+    __syncthreads();
+    carry = 0;
+    scan_chunk(bufc, wsum, &carry);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x;
+      if (i < nb) start[i] = bufc[scan_pad(i)];
+    }
+    if (threadIdx.x == 0) start[nb] = carry;
+    return;
+  }
   // bin-major: bin b carries T[b], the sum of its species counts
   for (int c0 = 0; c0 < n_bins; c0 += kScanChunk) {
 #pragma unroll

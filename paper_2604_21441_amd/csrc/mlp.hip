@@ -45,36 +45,63 @@ __device__ __forceinline__ v8bf to_bf16x8(const v4f& lo, const v4f& hi) {
   return r;
 }
 
+// Weight fragments are streamed from L2 with a prefetch ring: the loads for
+// K block kb + kPrefetch are issued before the products of block kb, so
+// several fragment loads are in flight behind the matrix-core work.  (The
+// wide H/C/N/O networks keep a shallower ring to stay clear of spills.)
+constexpr int kPrefetchNarrow = 3;
+constexpr int kPrefetchWide = 2;
+
+template <bool BF16>
+struct Frag {
+  using T = v4f;
+};
+template <>
+struct Frag<true> {
+  using T = v8bf;
+};
+
+__device__ __forceinline__ v4f mma(const v4f& w, const v4f& b, v4f c) { return mfma_step(w, b, c); }
+__device__ __forceinline__ v4f mma(const v8bf& w, const v8bf& b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, c, 0, 0, 0);
+}
+
 // out[R/16 tiles] (+)= W[R x C] * in[C/16 tiles]; `in` is register resident.
 // Row tiles are processed in chunks of CH to bound the live accumulators.
 template <int R, int C, bool BF16, int CH>
 __device__ __forceinline__ void gemm_regs(const void* __restrict__ W, const v4f* in, v4f* out, int lane) {
   static_assert(R % 16 == 0 && C % (BF16 ? 32 : 16) == 0, "tile sizes");
+  constexpr int kPrefetch = (R > 160 || C > 160) ? kPrefetchWide : kPrefetchNarrow;
   constexpr int RT = R / 16;
+  constexpr int KB = BF16 ? C / 32 : C / 16;
+  using F = typename Frag<BF16>::T;
+  const F* Wp = reinterpret_cast<const F*>(W);
 #pragma unroll
   for (int r0 = 0; r0 < RT; r0 += CH) {
-    if constexpr (!BF16) {
-      constexpr int KB = C / 16;
-      const v4f* Wp = reinterpret_cast<const v4f*>(W);
+    const int nr = (r0 + CH < RT ? CH : RT - r0);
+    F ring[kPrefetch][CH];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
+    for (int p = 0; p < kPrefetch; ++p)
 #pragma unroll
-        for (int r = r0; r < (r0 + CH < RT ? r0 + CH : RT); ++r) {
-          v4f w = Wp[(r * KB + kb) * 64 + lane];
-          out[r] = mfma_step(w, in[kb], out[r]);
-        }
+      for (int r = 0; r < CH; ++r)
+        if (p < KB && r < nr) ring[p][r] = Wp[((r0 + r) * KB + p) * 64 + lane];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      F cur[CH];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        cur[r] = ring[kb % kPrefetch][r];
+        if (kb + kPrefetch < KB && r < nr) ring[kb % kPrefetch][r] = Wp[((r0 + r) * KB + kb + kPrefetch) * 64 + lane];
       }
-    } else {
-      constexpr int KB = C / 32;
-      const v8bf* Wp = reinterpret_cast<const v8bf*>(W);
+      if constexpr (BF16) {
+        const v8bf b = to_bf16x8(in[2 * kb], in[2 * kb + 1]);
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        v8bf b = to_bf16x8(in[2 * kb], in[2 * kb + 1]);
+        for (int r = 0; r < CH; ++r)
+          if (r < nr) out[r0 + r] = mma(cur[r], b, out[r0 + r]);
+      } else {
 #pragma unroll
-        for (int r = r0; r < (r0 + CH < RT ? r0 + CH : RT); ++r) {
-          v8bf w = Wp[(r * KB + kb) * 64 + lane];
-          out[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, out[r], 0, 0, 0);
-        }
+        for (int r = 0; r < CH; ++r)
+          if (r < nr) out[r0 + r] = mma(cur[r], in[kb], out[r0 + r]);
       }
     }
   }
@@ -110,49 +137,48 @@ template <int R, int K, bool BF16, int C>
 __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* in, int in_tiles, v4f (*out)[C],
                                          int w, int lane) {
   constexpr int NJ = Own<R>::n;
-  if constexpr (!BF16) {
-    constexpr int KB = K / 16;
-    const v4f* Wp = reinterpret_cast<const v4f*>(W);
-#pragma unroll 2
-    for (int kb = 0; kb < KB; ++kb) {
-      v4f bv[C];
+  constexpr int KB = BF16 ? K / 32 : K / 16;
+  constexpr int kPrefetch = (16 * R > 160 || K > 160) ? kPrefetchWide : kPrefetchNarrow;
+  using F = typename Frag<BF16>::T;
+  const F* Wp = reinterpret_cast<const F*>(W);
+  F ring[kPrefetch][NJ];
 #pragma unroll
-      for (int c = 0; c < C; ++c) bv[c] = in[(c * in_tiles + kb) * 64 + lane];
+  for (int p = 0; p < kPrefetch; ++p)
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int r = w + kWaves * j;
-        if (r < R) {
-          const v4f wv = Wp[(r * KB + kb) * 64 + lane];
-#pragma unroll
-          for (int c = 0; c < C; ++c) out[j][c] = mfma_step(wv, bv[c], out[j][c]);
-        }
-      }
+    for (int j = 0; j < NJ; ++j) {
+      const int r = w + kWaves * j;
+      if (p < KB && r < R) ring[p][j] = Wp[(r * KB + p) * 64 + lane];
     }
-  } else {
-    constexpr int KB = K / 32;
-    const v8bf* Wp = reinterpret_cast<const v8bf*>(W);
-#pragma unroll 2
-    for (int kb = 0; kb < KB; ++kb) {
-      v8bf bv[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c)
+  for (int kb = 0; kb < KB; ++kb) {
+    F cur[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int r = w + kWaves * j;
+      cur[j] = ring[kb % kPrefetch][j];
+      if (kb + kPrefetch < KB && r < R) ring[kb % kPrefetch][j] = Wp[(r * KB + kb + kPrefetch) * 64 + lane];
+    }
+    F bv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if constexpr (BF16)
         bv[c] = to_bf16x8(in[(c * in_tiles + 2 * kb) * 64 + lane], in[(c * in_tiles + 2 * kb + 1) * 64 + lane]);
+      else
+        bv[c] = in[(c * in_tiles + kb) * 64 + lane];
+    }
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int r = w + kWaves * j;
-        if (r < R) {
-          const v8bf wv = Wp[(r * KB + kb) * 64 + lane];
+    for (int j = 0; j < NJ; ++j) {
+      const int r = w + kWaves * j;
+      if (r < R) {
 #pragma unroll
-          for (int c = 0; c < C; ++c)
-            out[j][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv, bv[c], out[j][c], 0, 0, 0);
-        }
+        for (int c = 0; c < C; ++c) out[j][c] = mma(cur[j], bv[c], out[j][c]);
       }
     }
   }
 }
 
 template <int K0, int N1, int N2, int N3, bool BF16, int C>
-__global__ __launch_bounds__(256) void k_mlp_split(MlpArgs a, float alpha) {
+__global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a, float alpha) {
   constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
   constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
   constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
