@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
                                                     int* __restrict__ perm,
                                                     float4* __restrict__ spos,
                                                     int* __restrict__ slot_atom,
-                                                    int* __restrict__ order) {
+                                                    int* __restrict__ order, int* __restrict__ sbin) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= n_bins_total) return;
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
     int slot = b0 + rank;
     perm[slot] = t;
     order[o0 + rank] = slot;
+    sbin[slot] = bin;
     const int a = idx[t];
     const float3 p = nnp_position(pos, a, L, g);
     spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sigma[t]));
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
                                                       Geometry g, LinkArgs L, const int* __restrict__ cmstart,
                                                       int* __restrict__ perm, float4* __restrict__ spos,
                                                       int* __restrict__ slot_atom, int* __restrict__ order,
-                                                      int* __restrict__ count) {
+                                                      int* __restrict__ count, int* __restrict__ sbin) {
   const int m = blockIdx.x;
   const int lane = threadIdx.x;
   if (lane < S) count[lane * n_sys + m] = 0;   // the histogram starts from zero in the next call
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
       const int a = idx[t];
       perm[slot] = t;
       order[cmstart[m * S + sg] + rank] = slot;
+      sbin[slot] = m;
       const float3 p = nnp_position(pos, a, L, g);
       spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sg));
       slot_atom[slot] = a;
@@ -337,6 +339,7 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
 
 struct NeighArgs {
   const int* order;        // bin-major visiting order of the slots
+  const int* sbin;         // bin of each slot
   const float4* spos;
   const int* perm;
   const int* key;
@@ -363,43 +366,61 @@ constexpr int kMaxStencil = 27;
 // sets the device status word.
 __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
 #pragma clang fp contract(off)
-  __shared__ int s_cell[kMaxStencil];
-  __shared__ int s_start[kMaxStencil];
-  __shared__ int s_off[kMaxStencil];
+  __shared__ int s_start[kMaxSpecies][kMaxStencil];
+  __shared__ int s_off[kMaxSpecies][kMaxStencil + 1];
   const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const float4 pi = a.spos[i];
-  const int bin = a.key[a.perm[i]] % g.n_bins;
+  const int bin = a.sbin[i];
+  // Stencil cells in ascending id order: per dimension the (wrapped) offsets
+  // are sorted, and ids are lexicographic in (x, y, z).
   int nst = 1;
-  int my_cell = -1;
+  int my_cell = bin;
   if (g.periodic) {
-    int c[3], nd[3];
+    int c[3], nd[3], v[3][3];
     c[0] = bin / (g.nc[1] * g.nc[2]);
     c[1] = (bin / g.nc[2]) % g.nc[1];
     c[2] = bin % g.nc[2];
-    for (int k = 0; k < 3; ++k) nd[k] = g.nc[k] >= 3 ? 3 : g.nc[k];
-    nst = nd[0] * nd[1] * nd[2];
-    if (lane < nst) {
-      int o[3] = {lane / (nd[1] * nd[2]), (lane / nd[2]) % nd[1], lane % nd[2]};
-      int w[3];
-      for (int k = 0; k < 3; ++k) {
-        // offsets {-1, 0, 1} for >= 3 cells, {0, 1} for 2 cells, {0} for 1 cell
-        int off = nd[k] == 3 ? o[k] - 1 : o[k];
-        int x = c[k] + off;
-        w[k] = x < 0 ? x + g.nc[k] : (x >= g.nc[k] ? x - g.nc[k] : x);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int n = g.nc[k];
+      nd[k] = n >= 3 ? 3 : n;
+      if (n >= 3) {        // {c-1, c, c+1} wrapped, ascending
+        if (c[k] == 0) { v[k][0] = 0; v[k][1] = 1; v[k][2] = n - 1; }
+        else if (c[k] == n - 1) { v[k][0] = 0; v[k][1] = n - 2; v[k][2] = n - 1; }
+        else { v[k][0] = c[k] - 1; v[k][1] = c[k]; v[k][2] = c[k] + 1; }
+      } else {             // every cell of the dimension
+        v[k][0] = 0; v[k][1] = 1; v[k][2] = 2;
       }
-      my_cell = (w[0] * g.nc[1] + w[1]) * g.nc[2] + w[2];
     }
-  } else if (lane == 0) {
-    my_cell = bin;
+    nst = nd[0] * nd[1] * nd[2];
+    const int l = lane < nst ? lane : 0;
+    const int o0 = l / (nd[1] * nd[2]), o1 = (l / nd[2]) % nd[1], o2 = l % nd[2];
+    my_cell = (v[0][o0] * g.nc[1] + v[1][o1]) * g.nc[2] + v[2][o2];
   }
-  // ascending order of the stencil cells (their ids are distinct)
-  int rank = 0;
-  for (int l = 0; l < nst; ++l) {
-    int o = __shfl(my_cell, l, 64);
-    rank += (o < my_cell) ? 1 : 0;
+  // candidate ranges of every species (one stencil cell per lane), prefix sums
+  int st[kMaxSpecies], total[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    int cnt = 0;
+    st[s] = 0;
+    if (s < a.S && lane < nst) {
+      const int b = s * g.n_bins + my_cell;
+      st[s] = a.bin_start[b];
+      cnt = a.bin_start[b + 1] - st[s];
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int u = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += u;
+    }
+    total[s] = __shfl(inc, nst - 1, 64);
+    if (s < a.S && lane < nst) {
+      s_start[s][lane] = st[s];
+      s_off[s][lane] = inc - cnt;
+    }
   }
-  if (lane < nst) s_cell[rank] = my_cell;
   __syncthreads();
 
   int* rad = a.rad + (int64_t)i * a.max_rad;
@@ -408,75 +429,75 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   const uint64_t lt = __lanemask_lt();
   int nr = 0, na = 0;
   bool overflow = false;
+  // candidate c of species s -> slot (binary search over the range starts)
+  auto slot_of = [&](int s, int c) {
+    int lo = 0, hi = nst - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[s][mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return s_start[s][lo] + (c - s_off[s][lo]);
+  };
+  auto test = [&](int j, bool& in_r, bool& in_a) {
+    in_r = in_a = false;
+    if (j < 0 || j == i) return;
+    const float4 pj = a.spos[j];
+    float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    if (g.periodic) {
+      float sx = rintf(dx * g.inv_box[0]);
+      float sy = rintf(dy * g.inv_box[1]);
+      float sz = rintf(dz * g.inv_box[2]);
+      float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+      dx = dx - tx; dy = dy - ty; dz = dz - tz;
+    }
+    float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    float r2 = xx + yy;
+    r2 = r2 + zz;
+    in_r = r2 < a.rc2;
+    in_a = r2 < a.rca2;
+  };
+  auto emit = [&](int j, bool in_r, bool in_a) {
+    const uint64_t mr = __ballot(in_r);
+    const int pr = nr + __popcll(mr & lt);
+    const bool in_a2 = in_a && pr < a.max_rad;   // angular entries point into the radial list
+    const uint64_t ma = __ballot(in_a2);
+    const int pa = na + __popcll(ma & lt);
+    if (in_r && pr < a.max_rad) rad[pr] = j;
+    if (in_a2 && pa < a.max_ang) {
+      ang[pa] = j;
+      angpos[pa] = pr;
+    }
+    nr += __popcll(mr);
+    na += __popcll(ma);
+    if (nr > a.max_rad || na > a.max_ang) {
+      overflow = true;
+      nr = min(nr, a.max_rad);
+      na = min(na, a.max_ang);
+    }
+  };
   for (int s = 0; s < a.S; ++s) {
     if (lane == 0) {
       a.rad_off[(int64_t)i * (a.S + 1) + s] = nr;
       a.ang_off[(int64_t)i * (a.S + 1) + s] = na;
     }
-    int st = 0, cnt = 0;
-    if (lane < nst) {
-      int b = s * g.n_bins + s_cell[lane];
-      st = a.bin_start[b];
-      cnt = a.bin_start[b + 1] - st;
-    }
-    int inc = cnt;
-    for (int off = 1; off < 32; off <<= 1) {
-      int v = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += v;
-    }
-    const int total = __shfl(inc, nst - 1, 64);
-    if (lane < nst) {
-      s_start[lane] = st;
-      s_off[lane] = inc - cnt;
-    }
-    __syncthreads();
-    for (int c0 = 0; c0 < total; c0 += 64) {
-      const int c = c0 + lane;
-      bool in_r = false, in_a = false;
-      int j = -1;
-      if (c < total) {
-        int lo = 0, hi = nst - 1;
-        while (lo < hi) {
-          int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
-        }
-        j = s_start[lo] + (c - s_off[lo]);
-        if (j != i) {
-          float4 pj = a.spos[j];
-          float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-          if (g.periodic) {
-            float sx = rintf(dx * g.inv_box[0]);
-            float sy = rintf(dy * g.inv_box[1]);
-            float sz = rintf(dz * g.inv_box[2]);
-            float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-            dx = dx - tx; dy = dy - ty; dz = dz - tz;
-          }
-          float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-          float r2 = xx + yy;
-          r2 = r2 + zz;
-          in_r = r2 < a.rc2;
-          in_a = r2 < a.rca2;
-        }
-      }
-      const uint64_t mr = __ballot(in_r);
-      const int pr = nr + __popcll(mr & lt);
-      const bool in_a2 = in_a && pr < a.max_rad;   // angular entries point into the radial list
-      const uint64_t ma = __ballot(in_a2);
-      const int pa = na + __popcll(ma & lt);
-      if (in_r && pr < a.max_rad) rad[pr] = j;
-      if (in_a2 && pa < a.max_ang) {
-        ang[pa] = j;
-        angpos[pa] = pr;
-      }
-      nr += __popcll(mr);
-      na += __popcll(ma);
-      if (nr > a.max_rad || na > a.max_ang) {
-        overflow = true;
-        nr = min(nr, a.max_rad);
-        na = min(na, a.max_ang);
+    // up to two candidates per lane per step (both positions loaded before
+    // either is tested); accepted ones are appended in candidate order
+    for (int c0 = 0; c0 < total[s]; c0 += 128) {
+      const int c1 = c0 + lane, c2 = c0 + 64 + lane;
+      const int j1 = c1 < total[s] ? slot_of(s, c1) : -1;
+      bool r1, a1;
+      if (c0 + 64 < total[s]) {
+        const int j2 = c2 < total[s] ? slot_of(s, c2) : -1;
+        bool r2, a2;
+        test(j1, r1, a1);
+        test(j2, r2, a2);
+        emit(j1, r1, a1);
+        emit(j2, r2, a2);
+      } else {
+        test(j1, r1, a1);
+        emit(j1, r1, a1);
       }
     }
-    __syncthreads();
   }
   if (lane == 0) {
     a.rad_off[(int64_t)i * (a.S + 1) + a.S] = nr;
@@ -657,14 +678,14 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   if (n > 0 && !g.periodic) {
     hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
                        m.d_sigma, m.d_idx, pos, g, L, m.d_cmstart, m.d_perm, m.d_spos, m.d_slot_atom,
-                       m.d_order, m.d_bin_count);
+                       m.d_order, m.d_bin_count, m.d_sbin);
   } else if (n > 0) {
     int* tmp = m.d_tmp;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
                        m.d_bin_start, m.d_bin_count, tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
                        m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
-                       m.d_spos, m.d_slot_atom, m.d_order);
+                       m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin);
   }
   return hipGetLastError();
 }
@@ -682,6 +703,7 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   NeighArgs a;
   a.order = m.d_order;
+  a.sbin = m.d_sbin;
   a.spos = m.d_spos;
   a.perm = m.d_perm;
   a.key = m.d_key;

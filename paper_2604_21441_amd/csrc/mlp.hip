@@ -49,8 +49,12 @@ __device__ __forceinline__ v8bf to_bf16x8(const v4f& lo, const v4f& hi) {
 // K block kb + kPrefetch are issued before the products of block kb, so
 // several fragment loads are in flight behind the matrix-core work.  (The
 // wide H/C/N/O networks keep a shallower ring to stay clear of spills.)
-constexpr int kPrefetchNarrow = 3;
-constexpr int kPrefetchWide = 2;
+// A BF16 step is an eighth of an FP32 step's matrix-core time, so its ring is
+// deeper.
+template <bool BF16, bool WIDE>
+struct PrefetchDepth {
+  static constexpr int value = WIDE ? (BF16 ? 3 : 2) : (BF16 ? 6 : 3);
+};
 
 template <bool BF16>
 struct Frag {
@@ -71,7 +75,7 @@ __device__ __forceinline__ v4f mma(const v8bf& w, const v8bf& b, v4f c) {
 template <int R, int C, bool BF16, int CH>
 __device__ __forceinline__ void gemm_regs(const void* __restrict__ W, const v4f* in, v4f* out, int lane) {
   static_assert(R % 16 == 0 && C % (BF16 ? 32 : 16) == 0, "tile sizes");
-  constexpr int kPrefetch = (R > 160 || C > 160) ? kPrefetchWide : kPrefetchNarrow;
+  constexpr int kPrefetch = PrefetchDepth<BF16, (R > 160 || C > 160)>::value;
   constexpr int RT = R / 16;
   constexpr int KB = BF16 ? C / 32 : C / 16;
   using F = typename Frag<BF16>::T;
@@ -138,7 +142,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
                                          int w, int lane) {
   constexpr int NJ = Own<R>::n;
   constexpr int KB = BF16 ? K / 32 : K / 16;
-  constexpr int kPrefetch = (16 * R > 160 || K > 160) ? kPrefetchWide : kPrefetchNarrow;
+  constexpr int kPrefetch = PrefetchDepth<BF16, (16 * R > 160 || K > 160)>::value;
   using F = typename Frag<BF16>::T;
   const F* Wp = reinterpret_cast<const F*>(W);
   F ring[kPrefetch][NJ];

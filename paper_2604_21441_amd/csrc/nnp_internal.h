@@ -141,6 +141,7 @@ struct nnp_model {
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
   float4* d_spos = nullptr;    // slot -> position (w = species bits)
   int* d_slot_atom = nullptr;  // slot -> atom index
+  int* d_sbin = nullptr;       // slot -> bin (cell or system)
   int* d_nbr_rad = nullptr;
   int* d_nbr_ang = nullptr;
   int* d_rad_off = nullptr;
