@@ -41,6 +41,7 @@ __all__ = [
     "species_index", "pair_class_table", "neighbour_pairs", "neighbour_pairs_bruteforce",
     "cutoff", "celu", "descriptors", "mlp_energies", "mlp_input_grad", "evaluate",
     "evaluate_batch", "cell_list_fp32", "neighbours_fp32", "mm_potential", "link_atom_positions",
+    "me_coupling",
 ]
 
 _F32 = np.float32
@@ -427,6 +428,46 @@ def link_atom_positions(r_ml, r_mm, d=1.0):
     r_mm = torch.as_tensor(r_mm, dtype=torch.float64)
     u = r_mm - r_ml
     return r_ml + d * u / torch.sqrt(torch.sum(u * u, dim=-1, keepdim=True))
+
+
+# --------------------------------------------------------------------------
+# Mechanical embedding (Theory, eq. 3): the ML-MM coupling stays at the MM
+# level -- Coulomb plus Lennard-Jones between every ML atom and every MM atom,
+# with fixed force-field charges and LJ parameters.  Readings: Lorentz-
+# Berthelot mixing (the rule of the GAFF and CHARMM force fields used in the
+# paper's Methods), a plain spherical cutoff without shift, minimum image.
+# --------------------------------------------------------------------------
+def me_coupling(ml_pos, ml_param, mm_pos, mm_param, ke, box=None, cutoff=None, forces=True, return_abs=False):
+    """E = sum_{i in ML} sum_{j in MM, r_ij < cutoff} ke q_i q_j / r_ij
+                                      + 4 eps_ij ((s_ij / r_ij)^12 - (s_ij / r_ij)^6),
+    s_ij = (s_i + s_j) / 2, eps_ij = sqrt(eps_i eps_j); param rows are (q, sigma, eps).
+    cutoff None takes every pair.  Returns (E, F_ml, F_mm) in float64 (forces by
+    autograd, F = -dE/dr), and with return_abs also sum_ij |pair energy|."""
+    x = torch.tensor(np.asarray(ml_pos, np.float64), requires_grad=forces)
+    y = torch.tensor(np.asarray(mm_pos, np.float64), requires_grad=forces)
+    pi = torch.as_tensor(np.asarray(ml_param, np.float64))
+    pj = torch.as_tensor(np.asarray(mm_param, np.float64))
+    d = y[None, :, :] - x[:, None, :]
+    if box is not None:
+        L = torch.as_tensor(np.asarray(box, np.float64))
+        d = d - L * torch.round(d / L)
+    r = torch.sqrt(torch.sum(d * d, dim=-1))
+    qq = pi[:, None, 0] * pj[None, :, 0]
+    sig = 0.5 * (pi[:, None, 1] + pj[None, :, 1])
+    eps = torch.sqrt(pi[:, None, 2] * pj[None, :, 2])
+    sr6 = (sig / r) ** 6
+    pair = ke * qq / r + 4.0 * eps * (sr6 * sr6 - sr6)
+    if cutoff is not None:
+        pair = torch.where(r < cutoff, pair, torch.zeros_like(pair))
+    E = pair.sum()
+    F_ml = F_mm = None
+    if forces:
+        gx, gy = torch.autograd.grad(E, (x, y))
+        F_ml, F_mm = (-gx).numpy(), (-gy).numpy()
+    out = (float(E.detach()), F_ml, F_mm)
+    if return_abs:
+        out = out + (float(pair.detach().abs().sum()),)
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -533,3 +533,78 @@ def test_link_atoms_chain_rule_fd(w_hcno):
             fd = -(orc.evaluate(p1, Z, HCNO, w_hcno, nnp_idx=idx, links=links, forces=False)["E"]
                    - orc.evaluate(p2, Z, HCNO, w_hcno, nnp_idx=idx, links=links, forces=False)["E"]) / (2 * h)
             assert abs(fd - ref["F"][a, k]) < 2e-7 * max(1.0, abs(ref["F"][a, k])), (a, k)
+
+
+# ------------------------------------------------- mechanical embedding (eq. 3)
+def _lj_coul_mp(r, qi, qj, si, sj, ei, ej, ke):
+    """Coulomb + 12-6 Lennard-Jones of one pair in 30-digit mpmath, Lorentz-Berthelot mixing."""
+    r = mpmath.mpf(r)
+    s = (mpmath.mpf(si) + mpmath.mpf(sj)) / 2
+    e = mpmath.sqrt(mpmath.mpf(ei) * mpmath.mpf(ej))
+    return mpmath.mpf(ke) * mpmath.mpf(qi) * mpmath.mpf(qj) / r + 4 * e * ((s / r) ** 12 - (s / r) ** 6)
+
+
+def test_me_coupling_dimer_closed_form():
+    pi = np.array([[0.41, 3.1, 0.0065]])
+    pj = np.array([[-0.834, 3.15, 0.0066]])
+    xi = np.array([[1.0, 2.0, 3.0]])
+    u = np.array([0.48, -0.6, 0.64])          # unit vector
+    r = 3.7
+    yj = xi + r * u
+    E, Fml, Fmm = orc.me_coupling(xi, pi, yj, pj, sy.KE_COULOMB)
+    args = (0.41, -0.834, 3.1, 3.15, 0.0065, 0.0066, sy.KE_COULOMB)
+    ref = _lj_coul_mp(r, *args)
+    dEdr = mpmath.diff(lambda t: _lj_coul_mp(t, *args), r)
+    assert abs(E - float(ref)) < 1e-13 * abs(float(ref))
+    np.testing.assert_allclose(Fmm[0], -float(dEdr) * u, rtol=1e-11, atol=1e-14)
+    np.testing.assert_allclose(Fml[0], float(dEdr) * u, rtol=1e-11, atol=1e-14)
+
+
+def test_me_coupling_lj_minimum():
+    """Neutral pair at r = 2^(1/6) sigma_ij: E = -eps_ij and no force."""
+    pi = np.array([[0.0, 2.9, 0.004]])
+    pj = np.array([[0.0, 3.3, 0.009]])
+    s, e = 3.1, math.sqrt(0.004 * 0.009)
+    r = 2.0 ** (1.0 / 6.0) * s
+    E, Fml, Fmm = orc.me_coupling(np.zeros((1, 3)), pi, np.array([[0.0, 0.0, r]]), pj, sy.KE_COULOMB)
+    assert abs(E + e) < 1e-15
+    assert np.abs(Fmm).max() < 1e-12 and np.abs(Fml).max() < 1e-12
+
+
+def test_me_coupling_cutoff_and_minimum_image():
+    """One MM atom inside the cutoff across the periodic boundary, one outside: the
+    energy is the closed-form dimer energy at the wrapped distance of the first."""
+    L = np.array([20.0, 20.0, 20.0])
+    pi = np.array([[0.3, 3.0, 0.005]])
+    pj = np.array([[-0.4, 3.2, 0.007], [0.9, 3.4, 0.008]])
+    xi = np.array([[0.5, 10.0, 10.0]])
+    yj = np.array([[19.0, 10.0, 10.0],       # 1.5 A away through the x boundary
+                   [0.5, 10.0, 18.0]])       # 8 A away, beyond the 6 A cutoff
+    E, _, Fmm = orc.me_coupling(xi, pi, yj, pj, sy.KE_COULOMB, box=L, cutoff=6.0)
+    ref = _lj_coul_mp(1.5, 0.3, -0.4, 3.0, 3.2, 0.005, 0.007, sy.KE_COULOMB)
+    assert abs(E - float(ref)) < 1e-12 * abs(float(ref))
+    assert np.all(Fmm[1] == 0.0)
+
+
+def test_me_coupling_third_law_and_fd():
+    rng = np.random.default_rng(5)
+    L = np.array([18.0, 18.0, 18.0])
+    ml = rng.uniform(6, 12, (7, 3))
+    mm = rng.uniform(0, 18, (40, 3))
+    pml = np.column_stack([rng.uniform(-0.5, 0.5, 7), rng.uniform(2.5, 3.8, 7), rng.uniform(0.001, 0.01, 7)])
+    pmm = np.column_stack([rng.uniform(-0.8, 0.8, 40), rng.uniform(2.5, 3.8, 40), rng.uniform(0.001, 0.01, 40)])
+    E, Fml, Fmm = orc.me_coupling(ml, pml, mm, pmm, sy.KE_COULOMB, box=L, cutoff=8.5)
+    tot = Fml.sum(0) + Fmm.sum(0)
+    assert np.abs(tot).max() < 1e-10 * np.abs(Fmm).max()
+    h = 1e-5
+    for arr, F, idx in ((ml, Fml, 3), (mm, Fmm, 11)):
+        for k in range(3):
+            p, m = arr.copy(), arr.copy()
+            p[idx, k] += h
+            m[idx, k] -= h
+            args_p = (p, pml, mm, pmm) if arr is ml else (ml, pml, p, pmm)
+            args_m = (m, pml, mm, pmm) if arr is ml else (ml, pml, m, pmm)
+            Ep = orc.me_coupling(*args_p, sy.KE_COULOMB, box=L, cutoff=8.5, forces=False)[0]
+            Em = orc.me_coupling(*args_m, sy.KE_COULOMB, box=L, cutoff=8.5, forces=False)[0]
+            fd = -(Ep - Em) / (2 * h)
+            assert abs(fd - F[idx, k]) < 1e-6 * max(1.0, abs(F[idx, k]))
