@@ -319,6 +319,35 @@ nnp_status nnp_profile_enable(nnp_model* m, int32_t max_calls);
  */
 nnp_status nnp_profile_read(nnp_model* m, double* ms_total, int64_t* calls, hipStream_t stream);
 
+/*
+ * Mechanical embedding (Theory, eq. 3): the ML-MM coupling term left at the MM
+ * level, Coulomb plus 12-6 Lennard-Jones between every ML atom i and every MM
+ * atom j, with the fixed charges and LJ parameters of the MM force field:
+ *   E = sum_i sum_{j: r_ij < cutoff} ke q_i q_j / r_ij
+ *                                    + 4 eps_ij ((s_ij / r_ij)^12 - (s_ij / r_ij)^6),
+ *   s_ij = (s_i + s_j) / 2,  eps_ij = sqrt(eps_i eps_j)   (Lorentz-Berthelot, the
+ *   rule of the GAFF and CHARMM force fields of the paper's Methods),
+ * with a plain spherical cutoff (no shift) and, when box_host is given, the
+ * minimum image.  It needs no model: every argument is given here.
+ *   ml_pos [n_ml][3], ml_param [n_ml][3] = (q, sigma, eps): device, FP32
+ *   mm_pos [n_mm][3], mm_param [n_mm][3]: device, FP32
+ *   box_host [3] (host) or NULL for open boundaries
+ *   cutoff > 0 (A); 0 takes every pair (open boundaries only)
+ *   ke: Coulomb constant in the caller's units (14.3996454784 eV A / e^2)
+ *   energy [1], ml_forces [n_ml][3], mm_forces [n_mm][3]: device, FP64, F = -dE/dr;
+ *   overwritten, or added to with accumulate = 1.
+ * Units follow the arguments (A, e, eV above).  Atoms must not coincide
+ * within the cutoff.  Launches on `stream` without synchronising; allocates
+ * nothing.  The ML forces and the energy are summed with FP64 atomics (last-
+ * bit differences between runs are possible); the MM forces are not.
+ * NNP_EINVAL for bad counts, pointers or cutoff; NNP_EBOX when a periodic box
+ * has no cutoff or one of its lengths is not above twice the cutoff.
+ */
+nnp_status nnp_me_coupling(int32_t n_ml, const float* ml_pos, const float* ml_param, int32_t n_mm,
+                           const float* mm_pos, const float* mm_param, const float* box_host, float cutoff,
+                           float ke, double* energy, double* ml_forces, double* mm_forces, int32_t accumulate,
+                           hipStream_t stream);
+
 /* Free the model, its weights and its workspace. */
 void nnp_destroy(nnp_model* m);
 

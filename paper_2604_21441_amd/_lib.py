@@ -81,6 +81,8 @@ SIGNATURES = {
     "nnp_autotune": (C.c_int, [_P, C.c_int32, _I32P, _P]),
     "nnp_set_variant": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "nnp_get_variants": (C.c_int, [_P, _I32P]),
+    "nnp_me_coupling": (C.c_int, [C.c_int32, _P, _P, C.c_int32, _P, _P, _F32P, C.c_float, C.c_float, _P, _P, _P,
+                                  C.c_int32, _P]),
     "nnp_profile_enable": (C.c_int, [_P, C.c_int32]),
     "nnp_profile_read": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64), _P]),
     "nnp_destroy": (None, [_P]),

@@ -834,6 +834,34 @@ nnp_status nnp_set_graph(nnp_model* m, int32_t enable) {
   return NNP_OK;
 }
 
+nnp_status nnp_me_coupling(int32_t n_ml, const float* ml_pos, const float* ml_param, int32_t n_mm,
+                           const float* mm_pos, const float* mm_param, const float* box_host, float cutoff,
+                           float ke, double* energy, double* ml_forces, double* mm_forces, int32_t accumulate,
+                           hipStream_t stream) {
+  if (n_ml < 0 || n_mm < 0) return set_error(NNP_EINVAL, "bad atom counts");
+  if (!energy || (n_ml > 0 && (!ml_pos || !ml_param || !ml_forces)) ||
+      (n_mm > 0 && (!mm_pos || !mm_param || !mm_forces)))
+    return set_error(NNP_EINVAL, "null array");
+  if (accumulate != 0 && accumulate != 1) return set_error(NNP_EINVAL, "accumulate must be 0 or 1");
+  if (!(cutoff >= 0.f) || !std::isfinite(cutoff) || !std::isfinite(ke))
+    return set_error(NNP_EINVAL, "cutoff must be finite and >= 0");
+  Geometry g{};
+  if (box_host) {
+    if (!(cutoff > 0.f)) return set_error(NNP_EBOX, "a periodic box needs a cutoff");
+    for (int k = 0; k < 3; ++k) {
+      if (!(box_host[k] > 2.f * cutoff) || !std::isfinite(box_host[k]))
+        return set_error(NNP_EBOX, "every box length must exceed twice the cutoff");
+      g.box[k] = box_host[k];
+      g.inv_box[k] = 1.f / box_host[k];
+    }
+    g.periodic = 1;
+  }
+  if (n_ml == 0 && n_mm == 0 && accumulate) return NNP_OK;
+  hipError_t e = launch_me_pairs(n_ml, ml_pos, ml_param, n_mm, mm_pos, mm_param, g, cutoff, ke, energy, ml_forces,
+                                 mm_forces, accumulate, stream);
+  return e == hipSuccess ? NNP_OK : hip_error(e, "nnp_me_coupling");
+}
+
 nnp_status nnp_set_variant(nnp_model* m, int32_t stage, int32_t variant) {
   if (!m) return set_error(NNP_EINVAL, "null model");
   if (stage < 0 || stage >= kTuneStages) return set_error(NNP_EINVAL, "unknown stage");

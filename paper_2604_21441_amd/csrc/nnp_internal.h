@@ -235,6 +235,9 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st);
 
 // fills (api.cpp)
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_me_pairs(int n_ml, const float* ml_pos, const float* ml_par, int n_mm, const float* mm_pos,
+                           const float* mm_par, const Geometry& g, float cutoff, float ke, double* energy,
+                           double* ml_f, double* mm_f, int accumulate, hipStream_t st);
 hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forces, hipStream_t st);
 
 }  // namespace nnp

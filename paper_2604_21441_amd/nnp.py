@@ -18,7 +18,7 @@ from . import _lib as L
 
 __all__ = [
     "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
-    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_variant", "nnp_get_variants", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
+    "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_variant", "nnp_get_variants", "nnp_me_coupling", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
 
@@ -131,6 +131,35 @@ def nnp_compute(h, pos: torch.Tensor, Z, box, nnp_idx, mm_pos, mm_q, energy: tor
                               _dptr(mm_forces, torch.float64, "mm_forces"), 1 if accumulate else 0,
                               _stream(stream))
     _check(st, "nnp_compute")
+
+
+KE_COULOMB = 14.3996454784   # eV * A / e^2
+
+
+def nnp_me_coupling(ml_pos: torch.Tensor, ml_param: torch.Tensor, mm_pos: torch.Tensor, mm_param: torch.Tensor,
+                    box=None, cutoff: float = 12.0, ke: float = KE_COULOMB, accumulate: bool = False, out=None,
+                    stream=None):
+    """Mechanical-embedding ML-MM coupling (eq. 3): Coulomb + Lennard-Jones over ML x MM pairs.
+
+    Params are [n, 3] FP32 CUDA tensors of (q, sigma, eps).  Returns (E [1], F_ml, F_mm) FP64
+    tensors (new ones unless `out` supplies them; with accumulate=True they are added to)."""
+    n_ml, n_mm = ml_pos.shape[0], mm_pos.shape[0]
+    dev = ml_pos.device if n_ml else mm_pos.device
+    if out is None:
+        E = torch.zeros(1, dtype=torch.float64, device=dev)
+        Fml = torch.zeros((n_ml, 3), dtype=torch.float64, device=dev)
+        Fmm = torch.zeros((n_mm, 3), dtype=torch.float64, device=dev)
+    else:
+        E, Fml, Fmm = out
+    Ba, Bp = _host(box, np.float32, "box")
+    st = L.load().nnp_me_coupling(n_ml, _dptr(ml_pos, torch.float32, "ml_pos"),
+                                  _dptr(ml_param, torch.float32, "ml_param"), n_mm,
+                                  _dptr(mm_pos, torch.float32, "mm_pos"), _dptr(mm_param, torch.float32, "mm_param"),
+                                  Bp, float(cutoff), float(ke), _dptr(E, torch.float64, "energy"),
+                                  _dptr(Fml, torch.float64, "ml_forces"), _dptr(Fmm, torch.float64, "mm_forces"),
+                                  1 if accumulate else 0, _stream(stream))
+    _check(st, "nnp_me_coupling")
+    return E, Fml, Fmm
 
 
 def nnp_compute_batch(h, offsets, pos: torch.Tensor, Z, energies: torch.Tensor, forces: torch.Tensor,

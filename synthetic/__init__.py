@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "model_config", "model_weights", "flat_weights", "splitmix64", "uniform01",
     "water_box", "walk_molecule", "walk_batch", "solute_in_water", "maxwell_boltzmann",
-    "WATER_MASS", "KE_COULOMB", "KB_EV", "ACC_UNIT",
+    "WATER_MASS", "KE_COULOMB", "KB_EV", "ACC_UNIT", "lj_params_solute", "lj_params_water",
 ]
 
 # Units: Angstrom, eV, elementary charge, amu, fs.
@@ -313,6 +313,29 @@ def solute_in_water(seed: int = 0, n_solute: int = 60, n_side: int = 22, L: floa
     mm_q = np.tile(np.array([-0.834, 0.417, 0.417], dtype=np.float32), n_keep)
     return {"pos": sp, "Z": sz, "mm_pos": np.ascontiguousarray(mm_pos), "mm_q": mm_q,
             "box": np.full(3, L, dtype=np.float32)}
+
+
+# Lennard-Jones parameters (sigma A, epsilon eV) of the order of general
+# force-field values per element, and TIP3P water (H carries no LJ site).
+_LJ_ELEMENT = {1: (2.50, 0.0013), 6: (3.40, 0.0037), 7: (3.25, 0.0073), 8: (3.00, 0.0091)}
+TIP3P = {"q": (-0.834, 0.417, 0.417), "sigma": (3.1507, 0.0, 0.0), "eps": (0.0065955, 0.0, 0.0)}
+
+
+def lj_params_solute(Z: np.ndarray, seed: int = 4) -> np.ndarray:
+    """[n, 3] float32 (q, sigma, eps) for a solute: element LJ values and seeded partial
+    charges U(-0.6, 0.6) shifted to a neutral total."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q = rng.uniform(-0.6, 0.6, len(Z))
+    q -= q.mean()
+    sig = np.array([_LJ_ELEMENT[int(z)][0] for z in Z])
+    eps = np.array([_LJ_ELEMENT[int(z)][1] for z in Z])
+    return np.ascontiguousarray(np.column_stack([q, sig, eps]).astype(np.float32))
+
+
+def lj_params_water(n_waters: int) -> np.ndarray:
+    """[3 n_waters, 3] float32 (q, sigma, eps) of TIP3P water in O, H, H order."""
+    one = np.column_stack([TIP3P["q"], TIP3P["sigma"], TIP3P["eps"]])
+    return np.ascontiguousarray(np.tile(one, (n_waters, 1)).astype(np.float32))
 
 
 def maxwell_boltzmann(Z: np.ndarray, T: float = 300.0, seed: int = 2) -> np.ndarray:

@@ -468,6 +468,41 @@ def test_mm_charge_channel(P):
     assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
 
 
+# ------------------------------------------- mechanical embedding (eq. 3)
+def test_me_coupling_parity(P):
+    """Coulomb + LJ over the 60 x 30,000 ML-MM pairs of the solvated solute, against the oracle:
+    periodic with a 12 A cutoff, and open with every pair; then accumulation and error paths."""
+    sysd = sy.solute_in_water(seed=0)
+    pml = sy.lj_params_solute(sysd["Z"])
+    pmm = sy.lj_params_water(len(sysd["mm_q"]) // 3)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    xml, qml, xmm, qmm = t(sysd["pos"]), t(pml), t(sysd["mm_pos"]), t(pmm)
+    for box, cutoff in ((sysd["box"], 12.0), (None, 0.0)):
+        E_ref, Fml_ref, Fmm_ref, Eabs = orc.me_coupling(sysd["pos"], pml, sysd["mm_pos"], pmm, sy.KE_COULOMB,
+                                                        box=box, cutoff=cutoff if cutoff > 0 else None,
+                                                        return_abs=True)
+        E, Fml, Fmm = P.nnp_me_coupling(xml, qml, xmm, qmm, box=box, cutoff=cutoff, ke=sy.KE_COULOMB)
+        torch.cuda.synchronize()
+        assert abs(E.item() - E_ref) < 1e-6 * Eabs
+        F = np.concatenate([Fml.cpu().numpy(), Fmm.cpu().numpy()])
+        F_ref = np.concatenate([Fml_ref, Fmm_ref])
+        assert rel_rmse(F, F_ref) < 1e-5
+        assert np.abs(F.sum(0)).max() < 1e-5 * np.abs(F).max() * math.sqrt(len(F))
+    # accumulate: a second call on the same outputs doubles them
+    out = P.nnp_me_coupling(xml, qml, xmm, qmm, box=sysd["box"], cutoff=12.0, ke=sy.KE_COULOMB)
+    E1, F1 = out[0].item(), out[2].clone()
+    P.nnp_me_coupling(xml, qml, xmm, qmm, box=sysd["box"], cutoff=12.0, ke=sy.KE_COULOMB, accumulate=True, out=out)
+    torch.cuda.synchronize()
+    assert abs(out[0].item() - 2 * E1) < 1e-9 * abs(E1)
+    assert torch.allclose(out[2], 2 * F1, rtol=1e-12, atol=0)
+    for kw, status in ((dict(box=sysd["box"], cutoff=0.0), P._lib.NNP_EBOX),
+                       (dict(box=sysd["box"], cutoff=40.0), P._lib.NNP_EBOX),
+                       (dict(box=None, cutoff=-1.0), P._lib.NNP_EINVAL)):
+        with pytest.raises(P.NNPError) as ex:
+            P.nnp_me_coupling(xml, qml, xmm, qmm, ke=sy.KE_COULOMB, **kw)
+        assert ex.value.status == status
+
+
 # ------------------------------------------------------------- error paths
 def test_error_paths(P, w_water):
     m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
