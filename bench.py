@@ -96,10 +96,13 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
     if stage == "descriptor":
         return ["k_desc_fwd", "k_desc_fwd_rows"][v.get("descriptor", 1)]
     if stage == "network":
-        nv = v.get("network", 1)
+        nv = v.get("network", 2)
         dims = f"{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {bf}"
-        return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {nv}>"
-    return {"adjoint": "k_desc_bwd", "gather": "k_force_gather",
+        cols = {1: 1, 2: 2, 3: 4 if k0 <= 128 else 2}.get(nv)
+        return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {cols}>"
+    if stage == "adjoint":
+        return ["k_desc_bwd<64>", "k_desc_bwd<32>"][v.get("adjoint", 0)]
+    return {"gather": "k_force_gather",
             "energy": "k_energy_final" if periodic else "k_energy"}.get(stage)
 
 

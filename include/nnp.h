@@ -232,17 +232,18 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
 
 /*
  * Autotuner.  Several stages have more than one kernel variant (network:
- * register-resident wavefronts or row-split workgroups of 16 or 32 atoms;
- * descriptor forward: a wavefront or a 16-lane row per atom; neighbour
- * search: one wavefront per atom or per cell).  nnp_autotune reruns the
+ * register-resident wavefronts or row-split workgroups of 16, 32 or 64 atoms;
+ * descriptor forward: a wavefront or a 16-lane row per atom; descriptor
+ * adjoint: a wavefront or half a wavefront per atom; neighbour search: one
+ * wavefront per atom or per cell).  nnp_autotune reruns the
  * stages after the cell list `reps` times (1..256) per candidate on the
  * workspace of the previous compute call (same size and geometry; the
  * caller's buffers are neither read nor written), times the stage being
  * tuned with events in that context, and keeps the fastest for that size
  * bucket (quarter octaves of the atom count); later calls of that size use
- * it.  Pinned stages (nnp_set_variant) are skipped.  chosen (host, [3] or
- * NULL) receives the variants now used for the neighbour, descriptor and
- * network stages, as nnp_get_variants.  Synchronises the stream; drops the
+ * it.  Pinned stages (nnp_set_variant) are skipped.  chosen (host, [4] or
+ * NULL) receives the variants now used for the neighbour, descriptor,
+ * network and adjoint stages, as nnp_get_variants.  Synchronises the stream; drops the
  * cached graph.  If the environment variable NNP_TUNE_CACHE names a file,
  * results are appended to it and read back by nnp_create for the same GPU
  * architecture and model shape.
@@ -253,7 +254,8 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
 typedef enum {
   NNP_TUNE_NEIGHBOURS = 0,
   NNP_TUNE_DESCRIPTOR = 1,
-  NNP_TUNE_NETWORK = 2
+  NNP_TUNE_NETWORK = 2,
+  NNP_TUNE_ADJOINT = 3
 } nnp_tune_stage;
 
 /*
@@ -262,14 +264,16 @@ typedef enum {
  * neighbours 0 one wavefront per atom, 1 one wavefront per cell (periodic
  * boxes; other geometries use 0); descriptor forward 0 one wavefront per
  * atom, 1 one 16-lane row per atom; network 0 register-resident wavefronts,
- * 1 / 2 row-split workgroups of 16 / 32 atoms.  All variants compute the same
+ * 1 / 2 / 3 row-split workgroups of 16 / 32 / 64 atoms (64: water-sized
+ * networks only, wider ones use 32); descriptor adjoint 0 one
+ * wavefront per atom, 1 half a wavefront per atom.  All variants compute the same
  * quantities (integer stages bit-identically, floating point to rounding).
  * Drops the cached graph.  NNP_EINVAL for an unknown stage or variant.
  */
 nnp_status nnp_set_variant(nnp_model* m, int32_t stage, int32_t variant);
 
 /*
- * The kernel variants (chosen[3], host, indexed by nnp_tune_stage) that a
+ * The kernel variants (chosen[4], host, indexed by nnp_tune_stage) that a
  * call of the size and geometry of the previous compute call runs: pinned,
  * else tuned, else the built-in default.  NNP_ESTATE before the first call.
  */

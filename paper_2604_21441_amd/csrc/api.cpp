@@ -745,7 +745,7 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
     timed(kTuneNeighbours, [&] { return launch_neighbours(*m, n, stream); });
     timed(kTuneDescriptor, [&] { return launch_descriptor_fwd(*m, n, stream); });
     timed(kTuneNetwork, [&] { return launch_mlp(*m, n, stream); });
-    timed(-1, [&] { return launch_descriptor_bwd(*m, n, stream); });
+    timed(kTuneAdjoint, [&] { return launch_descriptor_bwd(*m, n, stream); });
     return r;
   };
   auto time_stage = [&](int stage, int v, float* ms) -> nnp_status {
@@ -762,7 +762,7 @@ nnp_status nnp_autotune(nnp_model* m, int32_t reps, int32_t* chosen, hipStream_t
     m->force_variant[stage] = -1;
     return r == hipSuccess ? NNP_OK : hip_error(r, "nnp_autotune");
   };
-  const int stages[3] = {kTuneNetwork, kTuneDescriptor, kTuneNeighbours};
+  const int stages[4] = {kTuneNetwork, kTuneDescriptor, kTuneAdjoint, kTuneNeighbours};
   nnp_status status = NNP_OK;
   for (int st : stages) {
     if (m->pinned[st] >= 0) continue;   // a pinned stage keeps its variant
@@ -792,6 +792,7 @@ nnp_status nnp_get_variants(nnp_model* m, int32_t* chosen) {
   chosen[kTuneNeighbours] = neighbour_variant(*m, m->last_n);
   chosen[kTuneDescriptor] = descriptor_variant(*m, m->last_n);
   chosen[kTuneNetwork] = mlp_variant(*m, m->last_n);
+  chosen[kTuneAdjoint] = adjoint_variant(*m, m->last_n);
   return NNP_OK;
 }
 

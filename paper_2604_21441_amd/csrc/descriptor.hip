@@ -463,40 +463,58 @@ struct BwdArgs {
   double* self;      // [n][3]
 };
 
-__device__ __forceinline__ double wave_sum_d(double v) {
+// Sum over the LANES lanes of one atom (xor offsets below LANES stay inside it).
+template <int LANES>
+__device__ __forceinline__ double part_sum_d(double v) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = LANES / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
+// Bytes of LDS per atom of the adjoint: FP64 slots, the dE/dx row, padding to
+// 16 bytes, two float4 records per angular neighbour (a multiple of 16).
+__host__ __device__ __forceinline__ size_t bwd_lds_per_atom(int max_rad, int max_ang, int stride) {
+  return sizeof(double) * 3 * (size_t)max_rad + sizeof(float) * (size_t)stride +
+         sizeof(float) * 2 * ((size_t)max_rad & 1) + sizeof(float4) * 2 * (size_t)max_ang;
+}
+
+// LANES lanes per atom: 64 (one atom per wavefront) or 32 (two atoms per
+// wavefront, so that the ~153 triplets of an atom in water fill the lanes
+// with less rounding).
+template <int LANES>
 __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geometry geo) {
+  constexpr int APW = 64 / LANES;   // atoms per wavefront
   extern __shared__ double smem_d[];
-  double* sx = smem_d;                          // per radial neighbour, FP64
+  const int part = threadIdx.x / LANES;
+  const int lane = threadIdx.x % LANES;
+  char* region = reinterpret_cast<char*>(smem_d) + part * bwd_lds_per_atom(a.max_rad, a.max_ang, p.stride);
+  double* sx = reinterpret_cast<double*>(region);   // per radial neighbour, FP64
   double* sy = sx + a.max_rad;
   double* sz = sy + a.max_rad;
   float* gl = reinterpret_cast<float*>(sz + a.max_rad);   // [stride] dE/dx of the centre
   // angular neighbours: (u, r hq) and (fc sq_pref, dfc sq_pref, 1/r, radial position * 8 + species)
   float4* G1 = reinterpret_cast<float4*>(gl + p.stride + 2 * (a.max_rad & 1));   // 16-byte aligned
   float4* G2 = G1 + a.max_ang;
-  const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
-  const int lane = threadIdx.x;
+  const int li = xcd_block(blockIdx.x, gridDim.x) * APW + part;
+  const bool valid = li < a.n;
+  const int i = valid ? a.order[li] : 0;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
   const int S1 = p.S + 1;
-  const int nr = a.rad_off[(int64_t)i * S1 + p.S];
-  const int na = a.ang_off[(int64_t)i * S1 + p.S];
+  const int nr = valid ? a.rad_off[(int64_t)i * S1 + p.S] : 0;
+  const int na = valid ? a.ang_off[(int64_t)i * S1 + p.S] : 0;
   const int* rrow = a.rad + (int64_t)i * a.max_rad;
   const int* arow = a.ang + (int64_t)i * a.max_ang;
   float fx = 0.f, fy = 0.f, fz = 0.f;   // this lane's share of the centre's total
 
   // 1. dE/dx row
-  {
+  if (valid) {
     const float4* g4 = reinterpret_cast<const float4*>(a.g + (int64_t)i * p.stride);
     float4* l4 = reinterpret_cast<float4*>(gl);
-    for (int q = lane; q < p.D / 4; q += 64) l4[q] = g4[q];
+    for (int q = lane; q < p.D / 4; q += LANES) l4[q] = g4[q];
   }
   // 3. angular neighbour geometry (before the barrier, together with 1.)
-  for (int u = lane; u < na; u += 64) {
+  for (int u = lane; u < na; u += LANES) {
     const float4 pj = a.spos[arow[u]];
     Geo d = displacement(pi, pj, geo);
     const float arg = d.r * c.inv2rca;
@@ -508,7 +526,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   // 2. radial pairs
   {
     const float c1 = -2.f * p.eta_rad / p.sq_eta_r;   // d/dr of -(r sq - Rs sq)^2 per (r sq - Rs sq), in ln units
-    for (int t = lane; t < nr; t += 64) {
+    for (int t = lane; t < nr; t += LANES) {
 #pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
       const float4 pj = a.spos[rrow[t]];
       const int sj = __float_as_int(pj.w);
@@ -543,8 +561,8 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   __syncthreads();
   // 4. angular triplets (j < k, k-major), a contiguous range per lane
   const int T = na * (na - 1) / 2;
-  const int r0 = (int)(((int64_t)T * lane) >> 6);
-  const int r1 = (int)(((int64_t)T * (lane + 1)) >> 6);
+  const int r0 = (int)(((int64_t)T * lane) / LANES);
+  const int r1 = (int)(((int64_t)T * (lane + 1)) / LANES);
   if (r0 < r1) {
 #pragma clang fp contract(off)
     int k = (int)((1.f + __builtin_amdgcn_sqrtf(1.f + 8.f * (float)r0)) * 0.5f);
@@ -638,7 +656,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   __syncthreads();
   // 5. each neighbour's total goes to the centre's slot in the neighbour's list
   const int si = __float_as_int(pi.w);
-  for (int t = lane; t < nr; t += 64) {
+  for (int t = lane; t < nr; t += LANES) {
     const int j = rrow[t];
     const int* jrow = a.rad + (int64_t)j * a.max_rad;
     int lo = a.rad_off[(int64_t)j * S1 + si], hi = a.rad_off[(int64_t)j * S1 + si + 1] - 1;
@@ -650,8 +668,8 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
       a.contrib[(int64_t)j * a.max_rad + lo] = make_float4((float)-sx[t], (float)-sy[t], (float)-sz[t], 0.f);
   }
   // 6. the centre's own total
-  double dx = wave_sum_d((double)fx), dy = wave_sum_d((double)fy), dz = wave_sum_d((double)fz);
-  if (lane == 0) {
+  double dx = part_sum_d<LANES>((double)fx), dy = part_sum_d<LANES>((double)fy), dz = part_sum_d<LANES>((double)fz);
+  if (lane == 0 && valid) {
     a.self[3 * (int64_t)i + 0] = dx;
     a.self[3 * (int64_t)i + 1] = dy;
     a.self[3 * (int64_t)i + 2] = dz;
@@ -824,6 +842,13 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Adjoint variants: 0 = one wavefront per atom (default; measured faster on
+// water boxes), 1 = half a wavefront per atom.
+int adjoint_variant(const nnp_model& m, int n) {
+  const int v = stage_variant(m, kTuneAdjoint, n);
+  return v >= 0 ? v : 0;
+}
+
 hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   BwdArgs a;
@@ -840,10 +865,12 @@ hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   a.g = m.d_g;
   a.contrib = m.d_contrib;
   a.self = m.d_self;
-  // FP64 slots, the dE/dx row, padding to 16 bytes, two float4 records per angular neighbour
-  size_t lds = sizeof(double) * 3 * (size_t)m.max_rad + sizeof(float) * (size_t)m.stride +
-               sizeof(float) * 2 * ((size_t)m.max_rad & 1) + sizeof(float4) * 2 * (size_t)m.max_ang;
-  hipLaunchKernelGGL(k_desc_bwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);
+  const size_t per_atom = bwd_lds_per_atom(m.max_rad, m.max_ang, m.stride);
+  if (adjoint_variant(m, n) == 1) {
+    hipLaunchKernelGGL(k_desc_bwd<32>, dim3((n + 1) / 2), dim3(64), 2 * per_atom, st, a, m.dp, m.geo);
+  } else {
+    hipLaunchKernelGGL(k_desc_bwd<64>, dim3(n), dim3(64), per_atom, st, a, m.dp, m.geo);
+  }
   return hipGetLastError();
 }
 

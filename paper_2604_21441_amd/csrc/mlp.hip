@@ -607,7 +607,13 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
     const int64_t waves = (n + 15) / 16 + m.S;
     hipLaunchKernelGGL((k_mlp_reg<K0, N1, N2, N3, BF16>), dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, a, m.celu_alpha);
-  } else if (variant == 2) { // row split, 32 atoms per workgroup
+  } else if (variant == 3 && K0 <= 128) {   // row split, 64 atoms per workgroup (narrow networks)
+    if constexpr (K0 <= 128) {
+      const int64_t tiles = (n + 63) / 64 + m.S;
+      hipLaunchKernelGGL((k_mlp_split<K0, N1, N2, N3, BF16, 4>), dim3((unsigned)tiles), dim3(256), 0, st, a,
+                         m.celu_alpha);
+    }
+  } else if (variant >= 2) { // row split, 32 atoms per workgroup
     const int64_t tiles = (n + 31) / 32 + m.S;
     hipLaunchKernelGGL((k_mlp_split<K0, N1, N2, N3, BF16, 2>), dim3((unsigned)tiles), dim3(256), 0, st, a,
                        m.celu_alpha);
@@ -622,14 +628,14 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
 }  // namespace
 
 // Network kernel variant: 0 register-resident (16 atoms per wavefront),
-// 1 / 2 row split over 4 wavefronts with 16 / 32 atoms per workgroup.  A
-// tuned choice for this size wins; otherwise BF16 products are short enough
-// for the register-resident kernel, and FP32 ones need the row split.
+// 1 / 2 / 3 row split over 4 wavefronts with 16 / 32 / 64 atoms per workgroup
+// (64 only for the narrow water network; the wide one falls back to 32).  A
+// tuned choice for this size wins; otherwise the 32-atom row split, which
+// the tuner picked for the water boxes and the H/C/N/O batch in both forms.
 int mlp_variant(const nnp_model& m, int n) {
   int v = stage_variant(m, kTuneNetwork, n);
   if (v >= 0) return v;
-  if (m.prec == NNP_BF16) return 0;
-  return n >= 65536 ? 2 : 1;
+  return 2;
 }
 
 hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
@@ -651,7 +657,7 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
   const int v = mlp_variant(m, n);
-  m.mlp_cols = v == 2 ? 2 : 1;
+  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 ? 2 : 1);
   switch (m.net_kind) {
     case 0:
       return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, v, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, v, st);

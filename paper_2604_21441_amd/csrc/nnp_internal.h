@@ -22,7 +22,7 @@ constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
 constexpr int kTileAtoms = 16;   // atoms per wavefront in the network kernels
 
 // Stages with several kernel variants chosen by the autotuner.
-enum TuneStage { kTuneNeighbours = 0, kTuneDescriptor = 1, kTuneNetwork = 2, kTuneStages = 3 };
+enum TuneStage { kTuneNeighbours = 0, kTuneDescriptor = 1, kTuneNetwork = 2, kTuneAdjoint = 3, kTuneStages = 4 };
 
 // Workgroups are dispatched round-robin over the XCDs, each with its own L2.
 // xcd_block renumbers them so that every XCD works through one contiguous
@@ -113,8 +113,8 @@ struct nnp_model {
   nnp::DescParams dp{};
   int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
   std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
-  int force_variant[nnp::kTuneStages] = {-1, -1, -1};   // set while timing candidates
-  int pinned[nnp::kTuneStages] = {-1, -1, -1};          // nnp_set_variant
+  int force_variant[nnp::kTuneStages] = {-1, -1, -1, -1};   // set while timing candidates
+  int pinned[nnp::kTuneStages] = {-1, -1, -1, -1};          // nnp_set_variant
   int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
   std::vector<float> w_host;            // canonical FP32 weights, draw order
 
@@ -198,10 +198,11 @@ int tuned_choice(const nnp_model& m, int stage, int n);
 int descriptor_variant(const nnp_model& m, int n);
 int neighbour_variant(const nnp_model& m, int n);
 int mlp_variant(const nnp_model& m, int n);
+int adjoint_variant(const nnp_model& m, int n);
 // Variant of a tuned stage: the candidate being timed, else the pinned one,
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
-constexpr int kStageVariants[kTuneStages] = {2, 2, 3};
+constexpr int kStageVariants[kTuneStages] = {2, 2, 4, 2};
 int size_bucket(int n);
 
 // error helpers (api.cpp)

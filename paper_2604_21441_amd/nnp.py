@@ -193,17 +193,17 @@ def nnp_read_buffer(h, which: int, stream=None) -> np.ndarray:
 
 def nnp_autotune(h, reps: int = 5, stream=None) -> dict:
     """Time every kernel variant on the last call's workspace and keep the fastest."""
-    chosen = (C.c_int32 * 3)()
+    chosen = (C.c_int32 * 4)()
     _check(L.load().nnp_autotune(h, int(reps), chosen, _stream(stream)), "nnp_autotune")
-    return {"neighbours": chosen[0], "descriptor": chosen[1], "network": chosen[2]}
+    return {k: chosen[v] for k, v in TUNE_STAGES.items()}
 
 
-TUNE_STAGES = {"neighbours": 0, "descriptor": 1, "network": 2}
+TUNE_STAGES = {"neighbours": 0, "descriptor": 1, "network": 2, "adjoint": 3}
 
 
 def nnp_get_variants(h) -> dict:
     """Kernel variants a call of the previous call's size and geometry runs."""
-    chosen = (C.c_int32 * 3)()
+    chosen = (C.c_int32 * 4)()
     _check(L.load().nnp_get_variants(h, chosen), "nnp_get_variants")
     return {k: chosen[v] for k, v in TUNE_STAGES.items()}
 
