@@ -20,6 +20,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -270,14 +271,20 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
     if autotune:
         m.autotune(10)
     tuned = m.variants()
+    gc.collect()
+    gc.disable()   # a collector pause inside the timed loop would be charged to the library
     for _ in range(warmup):
         call()
     torch.cuda.synchronize()
+    host_ms = []
     t0 = time.perf_counter()
     for _ in range(steps):
+        tc = time.perf_counter()
         call()
+        host_ms.append(time.perf_counter() - tc)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     if m.status() != 0:
         raise RuntimeError("device status flagged an error during the timed steps")
     # per-stage event timing (stage launches issued directly; same kernels)
@@ -293,6 +300,7 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
     cnt = m.read(P._lib.NNP_BUF_NBR_COUNT)
     out = {
         "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "host_call_ms": {"median": statistics.median(host_ms) * 1e3, "max": max(host_ms) * 1e3},
         "profiled_ms_per_step": (tp1 - tp0) * 1e3 / steps,
         "stage_ms": {k: v / max(calls, 1) for k, v in stage_ms.items()},
         "E": E_first,
@@ -464,6 +472,7 @@ def main(argv=None):
         ref = oracle_reference(cfg, w, inp, sample)
     for prec, r in forms.items():
         entry = {"atom_steps_per_s": n / r["ms_per_step"] * 1e3, "ms_per_step": r["ms_per_step"],
+                 "host_call_ms": r["host_call_ms"],
                  "profiled_ms_per_step": r["profiled_ms_per_step"], "stage_ms": r["stage_ms"],
                  "tuned_variants": r["tuned"]}
         if ref is not None:

@@ -81,8 +81,6 @@ std::vector<uint8_t> make_key(const T&... parts) {
   return k;
 }
 
-// Run `launch` directly, or replay / capture it as a HIP graph.  Identical
-// calls (same key) replay one graph: a single launch instead of ~15.
 // Run `launch(stream)` directly, or replay / capture it as a HIP graph.
 // Identical calls (same key) replay one graph: one launch instead of ~15.
 // Capture happens on the model's own stream (the caller's may be the legacy
