@@ -130,7 +130,10 @@ def test_descriptors_fp32(P, water_models, boxes, oracle_res, name):
     xr[perm] = x
     ref = oracle_res[name]["x"]
     err = np.linalg.norm(xr - ref, axis=1) / np.linalg.norm(ref, axis=1)
-    assert err.max() < 1e-5, err.max()
+    # FP32 with hardware exp2/log2: the angular power (1 + cos)^zeta is exp2(zeta log2(.)),
+    # which multiplies log2's absolute error (~1e-7) by zeta = 14.1, so a row can carry a
+    # few 1e-6 of relative error; 5e-6 bounds that with margin.
+    assert err.max() < 5e-6, err.max()
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -248,6 +251,18 @@ def test_graph_replay_matches_eager(P, water_models, boxes):
         torch.cuda.synchronize()
         assert abs(E.item() - E0.item()) < 1e-12 * abs(E0.item()), rep
         assert torch.allclose(F, F0, rtol=0, atol=1e-12), rep
+    # a different size is a different configuration: captured anew, not replayed
+    pos_s, Z_s, box_s = boxes["c1"]
+    Es, Fs, _ = m.compute(torch.from_numpy(pos_s).cuda(), Z_s, box_s)
+    m.set_graph(False)
+    Es2, Fs2, _ = m.compute(torch.from_numpy(pos_s).cuda(), Z_s, box_s)
+    m.set_graph(True)
+    torch.cuda.synchronize()
+    assert abs(Es.item() - Es2.item()) < 1e-12 * abs(Es2.item())
+    assert torch.allclose(Fs, Fs2, rtol=0, atol=1e-12)
+    m.compute(d, Z, box, out=(E, F, None))
+    torch.cuda.synchronize()
+    assert abs(E.item() - E0.item()) < 1e-12 * abs(E0.item())
     # a moved configuration through the same graph gives the new answer
     d2 = d + 0.01
     torch.cuda.synchronize()
@@ -538,8 +553,11 @@ def test_error_paths(P, w_water):
 
 
 # ------------------------------------------- full-size sampled parity (98k)
-def test_c3_sampled_parity_fp32_bf16(P, water_models, w_water):
-    pos, Z, box = sy.water_box(32768, 99.4, seed=0)
+@pytest.mark.parametrize("n_mol,L", [(32768, 99.4), (87000, 137.7)], ids=["98304_atoms", "261000_atoms"])
+def test_large_box_sampled_parity_fp32_bf16(P, water_models, w_water, n_mol, L):
+    """Full-size boxes in the benchmark's launch configuration: exact oracle forces and
+    atomic energies on 24 sampled atoms; BF16 against FP32 over every atom."""
+    pos, Z, box = sy.water_box(n_mol, L, seed=0)
     res = {}
     for prec in ("fp32", "bf16"):
         E, F, _ = _run(water_models[prec], pos, Z, box)
