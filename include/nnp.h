@@ -166,6 +166,26 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
                        double* forces, double* mm_forces, int32_t accumulate, hipStream_t stream);
 
 /*
+ * As nnp_compute, but the neighbour lists come from the caller's pair list
+ * instead of the library's cell list (Methods: the 2026 interface also passes
+ * the pair list built by the MD engine).  pairs: device int32 [n_pairs][2],
+ * indices of the system's atoms, every unordered pair at most once (a half
+ * list); pairs may reach beyond the cutoff (a Verlet buffer: each pair of
+ * index-group atoms is re-tested with the same FP32 predicate as the cell
+ * list) and pairs with an atom outside the index group are ignored.  The list
+ * must hold every pair of index-group atoms closer than the radial cutoff;
+ * with such a list the neighbour lists, and so the results, are bit-identical
+ * to nnp_compute's.  A self pair, an out-of-range index or a repeated pair
+ * sets the device status (NNP_EINVAL from nnp_get_status).  Link atoms are
+ * not supported on this path (NNP_ESTATE); max_rad_nbr must be <= 256.
+ */
+nnp_status nnp_compute_pairs(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
+                             const float* box_host, int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_pairs,
+                             const int32_t* pairs, int32_t n_mm, const float* mm_pos, const float* mm_q,
+                             double* energy, double* forces, double* mm_forces, int32_t accumulate,
+                             hipStream_t stream);
+
+/*
  * Energies and forces of n_sys independent open (non-periodic) systems packed
  * back to back: system s owns atoms [atom_offsets_host[s], atom_offsets_host[s+1]).
  * All atoms are NNP atoms.  energies [n_sys] FP64, forces [total][3] FP64, both

@@ -123,7 +123,7 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
 void free_workspace(nnp_model* m) {
   dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_sys_off); dfree(m->d_key); dfree(m->d_bin_count);
   dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_spos);
-  dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
+  dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_loc); dfree(m->d_islot); dfree(m->d_pcount); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
   dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
@@ -362,6 +362,9 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_tmp, n));
   chk(dalloc(&m->d_slot_atom, n));
   chk(dalloc(&m->d_sbin, n));
+  chk(dalloc(&m->d_loc, n));
+  chk(dalloc(&m->d_islot, n));
+  chk(dalloc(&m->d_pcount, n));
   chk(dalloc(&m->d_spos, n));
   chk(dalloc(&m->d_bin_count, (size_t)m->max_bins));
   chk(dalloc(&m->d_bin_start, (size_t)m->max_bins + 1));
@@ -455,11 +458,14 @@ struct StageTimer {
 
 nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float* mm_pos, const float* mm_q,
                     double* energies, int n_sys, double* forces, double* mm_forces, int accumulate,
-                    int assign_forces, hipStream_t st) {
+                    int assign_forces, int n_atoms, int n_pairs, const int* pairs, hipStream_t st) {
   m->last_n = n;
   StageTimer tm(m, st);
   STAGE(NNP_STAGE_CELLS, launch_cells(*m, pos, n, st), "cell list");
-  STAGE(NNP_STAGE_NEIGHBOURS, launch_neighbours(*m, n, st), "neighbours");
+  if (pairs != nullptr || n_pairs > 0)
+    STAGE(NNP_STAGE_NEIGHBOURS, launch_pair_lists(*m, n, n_atoms, n_pairs, pairs, st), "pair lists");
+  else
+    STAGE(NNP_STAGE_NEIGHBOURS, launch_neighbours(*m, n, st), "neighbours");
   STAGE(NNP_STAGE_DESCRIPTOR, launch_descriptor_fwd(*m, n, st), "descriptor");
   if (m->extra) STAGE(NNP_STAGE_MM, launch_mm_fwd(*m, n, n_mm, mm_pos, mm_q, st), "mm channel");
   STAGE(NNP_STAGE_NETWORK, launch_mlp(*m, n, st), "network");
@@ -474,10 +480,15 @@ nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float
 
 }  // namespace
 
-nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host, const float* box_host,
-                       int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_mm, const float* mm_pos,
-                       const float* mm_q, double* energy, double* forces, double* mm_forces, int32_t accumulate,
-                       hipStream_t stream) {
+namespace {
+
+// One system (periodic box or open), neighbour lists from the cell list or,
+// with `pairs`, from the caller's pair list.
+nnp_status compute_single(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
+                          const float* box_host, int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_mm,
+                          const float* mm_pos, const float* mm_q, double* energy, double* forces,
+                          double* mm_forces, int32_t accumulate, int32_t n_pairs, const int32_t* pairs,
+                          hipStream_t stream) {
   if (!m) return set_error(NNP_EINVAL, "null model");
   if (!m->reserved) return set_error(NNP_ESTATE, "nnp_reserve must be called first");
   if (n_atoms < 0 || n_nnp < 0 || n_nnp > n_atoms) return set_error(NNP_EINVAL, "bad atom counts");
@@ -492,6 +503,14 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
     return set_error(NNP_EINVAL, "MM charges given to a model without the MM input channel");
   }
   if (accumulate != 0 && accumulate != 1) return set_error(NNP_EINVAL, "accumulate must be 0 or 1");
+
+  const bool pair_mode = pairs != nullptr || n_pairs != 0;
+  if (pair_mode) {
+    if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return set_error(NNP_EINVAL, "bad pair list");
+    if (m->n_links_dev > 0) return set_error(NNP_ESTATE, "link atoms are not supported with a caller's pair list");
+    if (m->max_rad > kPairRowMax)
+      return set_error(NNP_EINVAL, "pair lists need max_rad_nbr <= " + std::to_string(kPairRowMax));
+  }
 
   // topology (index group plus link atoms)
   const int n_links = m->n_links_dev;
@@ -533,6 +552,9 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
       if ((s = upload_ints(m, m->d_sigma, sig.data(), n_loc, stream)) != NNP_OK) return s;
       std::vector<int> zeros(n_loc, 0);  // an open single system is system 0
       if ((s = upload_ints(m, m->d_sys, zeros.data(), n_loc, stream)) != NNP_OK) return s;
+      std::vector<int> loc(n_atoms, -1);  // system atom -> NNP-local index (pair lists)
+      for (int t = 0; t < n_nnp; ++t) loc[idx[t]] = t;
+      if (n_atoms > 0 && (s = upload_ints(m, m->d_loc, loc.data(), n_atoms, stream)) != NNP_OK) return s;
       const int off[2] = {0, n_loc};
       if ((s = upload_ints(m, m->d_sys_off, off, 2, stream)) != NNP_OK) return s;
       m->topo_mode = 0;
@@ -573,17 +595,41 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
     if (n_links > 0 && (e = launch_fill_f64(m->d_link_F, 3 * (int64_t)n_links, s)) != hipSuccess)
       return hip_error(e, "fill");
     nnp_status st =
-        run_path(m, n_loc, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, assign, s);
+        run_path(m, n_loc, pos, n_mm, mm_pos, mm_q, energy, 1, forces, mm_forces, accumulate, assign, n_atoms, n_pairs,
+                 pairs, s);
     if (st != NNP_OK) return st;
     if (n_links > 0 && (e = launch_link_redistribute(*m, pos, forces, s)) != hipSuccess)
       return hip_error(e, "link atoms");
     return NNP_OK;
   };
-  const int mode = 0;
+  const int mode = pair_mode ? 2 : 0;
   const int lv = m->link_version;
   return dispatch(m, make_key(mode, pos, energy, forces, mm_forces, mm_pos, mm_q, n_atoms, n_nnp, n_mm, accumulate,
-                              lv, m->geo),
+                              lv, m->geo, n_pairs, pairs),
                   stream, launch);
+}
+
+}  // namespace
+
+nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host, const float* box_host,
+                       int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_mm, const float* mm_pos,
+                       const float* mm_q, double* energy, double* forces, double* mm_forces, int32_t accumulate,
+                       hipStream_t stream) {
+  return compute_single(m, n_atoms, pos, Z_host, box_host, n_nnp, nnp_idx_host, n_mm, mm_pos, mm_q, energy, forces,
+                        mm_forces, accumulate, 0, nullptr, stream);
+}
+
+nnp_status nnp_compute_pairs(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
+                             const float* box_host, int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_pairs,
+                             const int32_t* pairs, int32_t n_mm, const float* mm_pos, const float* mm_q,
+                             double* energy, double* forces, double* mm_forces, int32_t accumulate,
+                             hipStream_t stream) {
+  if (n_pairs > 0 && !pairs) return set_error(NNP_EINVAL, "null pair list");
+  if (n_pairs < 0) return set_error(NNP_EINVAL, "bad pair count");
+  // an empty list still selects the pair path (every NNP atom then has no neighbour)
+  static const int32_t kNone[2] = {0, 0};
+  return compute_single(m, n_atoms, pos, Z_host, box_host, n_nnp, nnp_idx_host, n_mm, mm_pos, mm_q, energy, forces,
+                        mm_forces, accumulate, n_pairs, pairs ? pairs : kNone, stream);
 }
 
 nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host, const float* pos,
@@ -636,7 +682,7 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
   m->last_n = n;
   auto launch = [=](hipStream_t s) -> nnp_status {
     // every atom of a batched call is an NNP atom: the gather overwrites each force row
-    return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, 1, s);
+    return run_path(m, n, pos, 0, nullptr, nullptr, energies, n_sys, forces, nullptr, 0, 1, n, 0, nullptr, s);
   };
   const int mode = 1;
   return dispatch(m, make_key(mode, pos, energies, forces, n, n_sys, m->geo), stream, launch);
@@ -650,6 +696,7 @@ nnp_status nnp_get_status(nnp_model* m, hipStream_t stream) {
   HIP_TRY(hipMemset(m->d_status, 0, sizeof(int)), "nnp_get_status");
   if (h & kStatusCapacity) return set_error(NNP_ECAPACITY, "a neighbour list overflowed its capacity");
   if (h & kStatusNonFinite) return set_error(NNP_ENONFINITE, "non-finite position or energy");
+  if (h & kStatusInput) return set_error(NNP_EINVAL, "the pair list held an out-of-range, self or repeated pair");
   return NNP_OK;
 }
 

@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
                                                     int* __restrict__ perm,
                                                     float4* __restrict__ spos,
                                                     int* __restrict__ slot_atom,
-                                                    int* __restrict__ order, int* __restrict__ sbin) {
+                                                    int* __restrict__ order, int* __restrict__ sbin,
+                                                    int* __restrict__ islot, int* __restrict__ pcount) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= n_bins_total) return;
@@ -283,6 +284,8 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
     perm[slot] = t;
     order[o0 + rank] = slot;
     sbin[slot] = bin;
+    islot[t] = slot;
+    pcount[slot] = 0;
     const int a = idx[t];
     const float3 p = nnp_position(pos, a, L, g);
     spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sigma[t]));
@@ -302,7 +305,8 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
                                                       Geometry g, LinkArgs L, const int* __restrict__ cmstart,
                                                       int* __restrict__ perm, float4* __restrict__ spos,
                                                       int* __restrict__ slot_atom, int* __restrict__ order,
-                                                      int* __restrict__ count, int* __restrict__ sbin) {
+                                                      int* __restrict__ count, int* __restrict__ sbin,
+                                                      int* __restrict__ islot, int* __restrict__ pcount) {
   const int m = blockIdx.x;
   const int lane = threadIdx.x;
   if (lane < S) count[lane * n_sys + m] = 0;   // the histogram starts from zero in the next call
@@ -330,6 +334,8 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
       perm[slot] = t;
       order[cmstart[m * S + sg] + rank] = slot;
       sbin[slot] = m;
+      islot[t] = slot;
+      pcount[slot] = 0;
       const float3 p = nnp_position(pos, a, L, g);
       spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sg));
       slot_atom[slot] = a;
@@ -661,6 +667,128 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Neighbour lists from a pair list supplied by the caller (the MD engine's own
+// list, a half list possibly with a buffer beyond the cutoff).  Each pair of
+// NNP atoms is re-tested with the same FP32 predicate as the cell-list search
+// and appended to both atoms' radial rows in arbitrary order; one wavefront
+// per row then sorts it by slot (which groups it by species, slots being
+// species-major), derives the species segments and the angular sub-list, so
+// the lists are exactly the ones the cell-list search builds.
+__device__ __forceinline__ float pair_r2(const float4& pi, const float4& pj, const Geometry& g) {
+#pragma clang fp contract(off)
+  float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  if (g.periodic) {
+    float sx = rintf(dx * g.inv_box[0]);
+    float sy = rintf(dy * g.inv_box[1]);
+    float sz = rintf(dz * g.inv_box[2]);
+    float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+    dx = dx - tx; dy = dy - ty; dz = dz - tz;
+  }
+  float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+  float r2 = xx + yy;
+  return r2 + zz;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairs_scatter(const int* __restrict__ pairs, int n_pairs,
+                                                          const int* __restrict__ loc, int n_atoms,
+                                                          const int* __restrict__ islot,
+                                                          const float4* __restrict__ spos, Geometry g, float rc2,
+                                                          int* __restrict__ rad, int* __restrict__ pcount,
+                                                          int max_rad, int* __restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int a = pairs[2 * (int64_t)p], b = pairs[2 * (int64_t)p + 1];
+  if (a < 0 || b < 0 || a >= n_atoms || b >= n_atoms || a == b) {
+    atomicOr(status, kStatusInput);
+    return;
+  }
+  const int la = loc[a], lb = loc[b];
+  if (la < 0 || lb < 0) return;   // a pair with an atom outside the index group
+  const int sa = islot[la], sb = islot[lb];
+  if (!(pair_r2(spos[sa], spos[sb], g) < rc2)) return;
+  const int pa = atomicAdd(&pcount[sa], 1), pb = atomicAdd(&pcount[sb], 1);
+  if (pa < max_rad) rad[(int64_t)sa * max_rad + pa] = sb;
+  if (pb < max_rad) rad[(int64_t)sb * max_rad + pb] = sa;
+}
+
+// One wavefront per slot: bitonic sort of the row (padded to a power of two,
+// at most kPairRowMax entries), then the species offsets and the angular list.
+constexpr int kPairSort = kPairRowMax;
+
+__global__ __launch_bounds__(64) void k_pairs_lists(NeighArgs a, Geometry g, const int* __restrict__ pcount) {
+  __shared__ int row[kPairSort];
+  __shared__ int arow[kPairSort];   // angular entries (slots), for the species counts
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int cnt = pcount[i];
+  bool overflow = cnt > a.max_rad;
+  const int n = min(cnt, a.max_rad);
+  int P = 64;
+  while (P < n) P <<= 1;
+  int* rrow = a.rad + (int64_t)i * a.max_rad;
+  for (int t = lane; t < P; t += 64) row[t] = t < n ? rrow[t] : 0x7fffffff;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < P; t += 64) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int x = row[t], y = row[u];
+          const bool up = (t & k) == 0;
+          if ((x > y) == up) {
+            row[t] = y;
+            row[u] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const float4 pi = a.spos[i];
+  const uint64_t lt = __lanemask_lt();
+  int* ang = a.ang + (int64_t)i * a.max_ang;
+  int* angpos = a.angpos + (int64_t)i * a.max_ang;
+  int na = 0;
+  bool dup = false;
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int t = c0 + lane;
+    int j = -1;
+    bool in_a = false;
+    if (t < n) {
+      j = row[t];
+      rrow[t] = j;
+      if (t > 0 && row[t - 1] == j) dup = true;
+      in_a = pair_r2(pi, a.spos[j], g) < a.rca2;
+    }
+    const uint64_t ma = __ballot(in_a);
+    const int pa = na + __popcll(ma & lt);
+    if (in_a && pa < a.max_ang) {
+      ang[pa] = j;
+      angpos[pa] = t;
+      arow[pa] = j;
+    }
+    na += __popcll(ma);
+  }
+  __syncthreads();
+  if (na > a.max_ang) {
+    overflow = true;
+    na = a.max_ang;
+  }
+  // species segments: slots below each species' first slot
+  if (lane <= a.S) {
+    const int bound = lane < a.S ? a.bin_start[lane * g.n_bins] : 0x7fffffff;
+    int r = 0, q = 0;
+    for (int t = 0; t < n; ++t) r += row[t] < bound;
+    for (int t = 0; t < na; ++t) q += arow[t] < bound;
+    if (lane == a.S) { r = n; q = na; }
+    a.rad_off[(int64_t)i * (a.S + 1) + lane] = r;
+    a.ang_off[(int64_t)i * (a.S + 1) + lane] = q;
+  }
+  if (lane == 0 && overflow) atomicOr(a.status, kStatusCapacity);
+  if (__ballot(dup) != 0 && lane == 0) atomicOr(a.status, kStatusInput);
+}
+
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -678,14 +806,14 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   if (n > 0 && !g.periodic) {
     hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
                        m.d_sigma, m.d_idx, pos, g, L, m.d_cmstart, m.d_perm, m.d_spos, m.d_slot_atom,
-                       m.d_order, m.d_bin_count, m.d_sbin);
+                       m.d_order, m.d_bin_count, m.d_sbin, m.d_islot, m.d_pcount);
   } else if (n > 0) {
     int* tmp = m.d_tmp;
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
                        m.d_bin_start, m.d_bin_count, tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
                        m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
-                       m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin);
+                       m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin, m.d_islot, m.d_pcount);
   }
   return hipGetLastError();
 }
@@ -725,6 +853,36 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   } else {
     hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_lists(nnp_model& m, int n, int n_atoms, int n_pairs, const int* pairs, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (n_pairs > 0) {
+    hipLaunchKernelGGL(k_pairs_scatter, dim3(blocks_for(n_pairs, kBlock)), dim3(kBlock), 0, st, pairs, n_pairs,
+                       m.d_loc, n_atoms, m.d_islot, m.d_spos, m.geo, m.dp.rc_rad * m.dp.rc_rad, m.d_nbr_rad,
+                       m.d_pcount, m.max_rad, m.d_status);
+  }
+  NeighArgs a;
+  a.order = m.d_order;
+  a.sbin = m.d_sbin;
+  a.spos = m.d_spos;
+  a.perm = m.d_perm;
+  a.key = m.d_key;
+  a.bin_start = m.d_bin_start;
+  a.n = n;
+  a.S = m.S;
+  a.rc2 = m.dp.rc_rad * m.dp.rc_rad;
+  a.rca2 = m.dp.rc_ang * m.dp.rc_ang;
+  a.rad = m.d_nbr_rad;
+  a.ang = m.d_nbr_ang;
+  a.angpos = m.d_angpos;
+  a.rad_off = m.d_rad_off;
+  a.ang_off = m.d_ang_off;
+  a.max_rad = m.max_rad;
+  a.max_ang = m.max_ang;
+  a.status = m.d_status;
+  hipLaunchKernelGGL(k_pairs_lists, dim3(n), dim3(64), 0, st, a, m.geo, m.d_pcount);
   return hipGetLastError();
 }
 

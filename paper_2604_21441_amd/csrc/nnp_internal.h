@@ -38,6 +38,8 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
 // Device status bits.
 constexpr int kStatusCapacity = 1;
 constexpr int kStatusNonFinite = 2;
+constexpr int kStatusInput = 4;      // bad entry in a caller's pair list
+constexpr int kPairRowMax = 256;     // radial capacity the pair-list sort supports
 
 // Descriptor constants, passed by value to the kernels.
 struct DescParams {
@@ -142,6 +144,9 @@ struct nnp_model {
   float4* d_spos = nullptr;    // slot -> position (w = species bits)
   int* d_slot_atom = nullptr;  // slot -> atom index
   int* d_sbin = nullptr;       // slot -> bin (cell or system)
+  int* d_loc = nullptr;        // system atom -> NNP-local index or -1 (pair lists)
+  int* d_islot = nullptr;      // NNP-local index -> slot
+  int* d_pcount = nullptr;     // radial entries per slot while a pair list is scattered
   int* d_nbr_rad = nullptr;
   int* d_nbr_ang = nullptr;
   int* d_rad_off = nullptr;
@@ -218,6 +223,7 @@ void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<flo
 // cells.hip
 hipError_t launch_cells(nnp_model& m, const float* pos, int n_nnp, hipStream_t st);
 hipError_t launch_neighbours(nnp_model& m, int n_nnp, hipStream_t st);
+hipError_t launch_pair_lists(nnp_model& m, int n, int n_atoms, int n_pairs, const int* pairs, hipStream_t st);
 
 // descriptor.hip
 hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st);

@@ -17,7 +17,7 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_batch", "nnp_get_status",
+    "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_pairs", "nnp_compute_batch", "nnp_get_status",
     "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_variant", "nnp_get_variants", "nnp_me_coupling", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
@@ -162,6 +162,25 @@ def nnp_me_coupling(ml_pos: torch.Tensor, ml_param: torch.Tensor, mm_pos: torch.
     return E, Fml, Fmm
 
 
+def nnp_compute_pairs(h, pos: torch.Tensor, Z, box, nnp_idx, pairs: torch.Tensor, mm_pos, mm_q,
+                      energy: torch.Tensor, forces: torch.Tensor, mm_forces=None, accumulate: bool = False,
+                      stream=None) -> None:
+    """nnp_compute with the neighbour lists taken from a caller's [n_pairs, 2] int32 CUDA pair list."""
+    n = pos.shape[0]
+    Za, Zp = _host(Z, np.int32, "Z")
+    Ia, Ip = _host(nnp_idx, np.int32, "nnp_idx")
+    Ba, Bp = _host(box, np.float32, "box")
+    n_nnp = n if Ia is None else Ia.size
+    n_mm = 0 if mm_pos is None else mm_pos.shape[0]
+    st = L.load().nnp_compute_pairs(h, n, _dptr(pos, torch.float32, "pos"), Zp, Bp, n_nnp, Ip, pairs.shape[0],
+                                    _dptr(pairs, torch.int32, "pairs"), n_mm,
+                                    _dptr(mm_pos, torch.float32, "mm_pos"), _dptr(mm_q, torch.float32, "mm_q"),
+                                    _dptr(energy, torch.float64, "energy"), _dptr(forces, torch.float64, "forces"),
+                                    _dptr(mm_forces, torch.float64, "mm_forces"), 1 if accumulate else 0,
+                                    _stream(stream))
+    _check(st, "nnp_compute_pairs")
+
+
 def nnp_compute_batch(h, offsets, pos: torch.Tensor, Z, energies: torch.Tensor, forces: torch.Tensor,
                       stream=None) -> None:
     Oa, Op = _host(offsets, np.int32, "offsets")
@@ -283,6 +302,21 @@ class NNPModel:
             Fmm = None if mm_pos is None else torch.empty((mm_pos.shape[0], 3), dtype=torch.float64, device=dev)
         nnp_compute(self.h, pos, Z, box, nnp_idx, mm_pos, mm_q, E, F, Fmm,
                     accumulate=accumulate_into is not None, stream=stream)
+        return E, F, Fmm
+
+    def compute_pairs(self, pos: torch.Tensor, pairs: torch.Tensor, Z=None, box=None, nnp_idx=None, mm_pos=None,
+                      mm_q=None, out=None, stream=None):
+        """As compute, with the neighbour lists built from a [n_pairs, 2] int32 CUDA half pair list."""
+        n = pos.shape[0]
+        self._ensure(n, 1, 0 if mm_pos is None else mm_pos.shape[0])
+        dev = pos.device
+        if out is not None:
+            E, F, Fmm = out
+        else:
+            E = torch.empty(1, dtype=torch.float64, device=dev)
+            F = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            Fmm = None if mm_pos is None else torch.empty((mm_pos.shape[0], 3), dtype=torch.float64, device=dev)
+        nnp_compute_pairs(self.h, pos, Z, box, nnp_idx, pairs, mm_pos, mm_q, E, F, Fmm, stream=stream)
         return E, F, Fmm
 
     def compute_batch(self, pos: torch.Tensor, Z, offsets, out=None, stream=None):

@@ -486,6 +486,67 @@ def test_mm_charge_channel(P):
     assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
 
 
+# ------------------------------------------------- caller's pair list (Methods)
+def _half_pairs(pos, box, r_list, rng, extra_far=500):
+    """Half pair list of every pair closer than r_list (float64), in shuffled order, with
+    some far pairs mixed in (the engine's list may reach beyond the cutoff)."""
+    I, J = orc.neighbour_pairs(pos, r_list, box)
+    keep = I < J
+    P = np.stack([I[keep], J[keep]], axis=1)
+    far = rng.integers(0, len(pos), size=(extra_far, 2))
+    far = far[far[:, 0] < far[:, 1]]
+    P = np.unique(np.concatenate([P, far]), axis=0)
+    P = P[rng.permutation(len(P))]
+    return np.ascontiguousarray(P.astype(np.int32))
+
+
+def test_pair_list_path_matches_cell_list(P, w_water, boxes):
+    """With the engine's pair list (cutoff plus a 0.5 A buffer) the lists, the energy and the
+    forces are bit-identical to the cell-list path; also for an index group."""
+    rng = np.random.default_rng(11)
+    pos, Z, box = boxes["c2"]
+    pairs = torch.from_numpy(_half_pairs(pos, box, WATER["rc_rad"] + 0.5, rng)).cuda()
+    d = torch.from_numpy(pos).cuda()
+    for idx in (None, np.sort(rng.choice(len(Z), 9000, replace=False)).astype(np.int32)):
+        a = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+        b = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+        Ea, Fa, _ = a.compute(d, Z, box, nnp_idx=idx)
+        Eb, Fb, _ = b.compute_pairs(d, pairs, Z, box, nnp_idx=idx)
+        torch.cuda.synchronize()
+        assert a.status() == 0 and b.status() == 0
+        for buf in (P._lib.NNP_BUF_NBR_COUNT, P._lib.NNP_BUF_NBR_RAD, P._lib.NNP_BUF_NBR_ANG, P._lib.NNP_BUF_PERM):
+            ra, rb = a.read(buf), b.read(buf)
+            if buf in (P._lib.NNP_BUF_NBR_RAD, P._lib.NNP_BUF_NBR_ANG):
+                cnt = a.read(P._lib.NNP_BUF_NBR_COUNT)[:, 0 if buf == P._lib.NNP_BUF_NBR_RAD else 1]
+                mask = np.arange(ra.shape[1])[None, :] < cnt[:, None]
+                ra, rb = np.where(mask, ra, -1), np.where(mask, rb, -1)
+            assert np.array_equal(ra, rb), buf
+        assert Ea.item() == Eb.item()
+        assert torch.equal(Fa, Fb)
+        # a second call through the captured graph, with the pair list reused
+        Eb2, Fb2, _ = b.compute_pairs(d, pairs, None, box, nnp_idx=idx)
+        torch.cuda.synchronize()
+        assert Eb2.item() == Ea.item()
+        a.close()
+        b.close()
+
+
+def test_pair_list_bad_entries(P, w_water, boxes):
+    pos, Z, box = boxes["c1"]
+    m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+    d = torch.from_numpy(pos).cuda()
+    for bad in ([[0, 0]], [[0, len(Z)]], [[3, 7], [3, 7]]):
+        pairs = torch.tensor(bad, dtype=torch.int32, device="cuda")
+        if bad == [[3, 7], [3, 7]]:
+            pos2 = pos.copy()
+            pos2[7] = pos2[3] + np.array([1.5, 0.0, 0.0], np.float32)   # make the repeated pair a real one
+            d = torch.from_numpy(pos2).cuda()
+        m.compute_pairs(d, pairs, Z, box)
+        torch.cuda.synchronize()
+        assert m.status() == P._lib.NNP_EINVAL, bad
+    m.close()
+
+
 # ------------------------------------------- mechanical embedding (eq. 3)
 def test_me_coupling_parity(P):
     """Coulomb + LJ over the 60 x 30,000 ML-MM pairs of the solvated solute, against the oracle:
