@@ -93,7 +93,7 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
     bf = "true" if prec == "bf16" else "false"
     v = variants or {}
     if stage == "neighbours":
-        return ["k_neighbours", "k_neighbours_cell"][v.get("neighbours", 0)]
+        return "k_neighbours" if v.get("neighbours", 0) == 0 else "k_neighbours_cell"
     if stage == "descriptor":
         return ["k_desc_fwd", "k_desc_fwd_rows"][v.get("descriptor", 1)]
     if stage == "network":

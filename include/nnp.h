@@ -255,7 +255,8 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
  * register-resident wavefronts or row-split workgroups of 16, 32 or 64 atoms;
  * descriptor forward: a wavefront or a 16-lane row per atom; descriptor
  * adjoint: a wavefront or half a wavefront per atom; neighbour search: one
- * wavefront per atom or per cell).  nnp_autotune reruns the
+ * wavefront per atom, or several per cell sharing its centre atoms).
+ * nnp_autotune reruns the
  * stages after the cell list `reps` times (1..256) per candidate on the
  * workspace of the previous compute call (same size and geometry; the
  * caller's buffers are neither read nor written), times the stage being
@@ -281,8 +282,8 @@ typedef enum {
 /*
  * Pin the kernel variant of one stage for later calls, overriding the tuned
  * choice and the built-in default; variant = -1 removes the pin.  Variants:
- * neighbours 0 one wavefront per atom, 1 one wavefront per cell (periodic
- * boxes; other geometries use 0); descriptor forward 0 one wavefront per
+ * neighbours 0 one wavefront per atom, 1 / 2 / 3 wavefronts per cell with
+ * about 8 / 5 / 3 centre atoms each (with one bin, 0 is used); descriptor forward 0 one wavefront per
  * atom, 1 one 16-lane row per atom; network 0 register-resident wavefronts,
  * 1 / 2 / 3 row-split workgroups of 16 / 32 / 64 atoms (64: water-sized
  * networks only, wider ones use 32); descriptor adjoint 0 one

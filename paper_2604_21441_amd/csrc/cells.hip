@@ -8,6 +8,8 @@
 // fixed order with floating-point contraction disabled, so an FP32 reference
 // that performs the same operations reproduces the bins, the permutation and
 // the neighbour sets bit for bit.
+#include <algorithm>
+
 #include "nnp_internal.h"
 
 namespace nnp {
@@ -519,55 +521,60 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
 // centre's accepted candidates being compacted with a ballot.  The stencil is
 // set up once per bin instead of once per atom.  Per-centre list lengths live
 // in the register of the lane with the centre's index.
-__global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g) {
+__global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g, int K) {
 #pragma clang fp contract(off)
-  __shared__ int s_cell[kMaxStencil];
   __shared__ int s_start[kMaxStencil];
   __shared__ int s_off[kMaxStencil];
   __shared__ float4 s_cpos[64];
   __shared__ int s_cid[64];
-  const int cell = xcd_block(blockIdx.x, gridDim.x);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int cell = b / K, part = b - cell * K;
   const int lane = threadIdx.x;
+  // stencil cells in ascending id order (see k_neighbours)
   int nst = 1;
-  int my_cell = -1;
+  int my_cell = cell;
   if (g.periodic) {
-    int c[3], nd[3];
+    int c[3], nd[3], v[3][3];
     c[0] = cell / (g.nc[1] * g.nc[2]);
     c[1] = (cell / g.nc[2]) % g.nc[1];
     c[2] = cell % g.nc[2];
-    for (int k = 0; k < 3; ++k) nd[k] = g.nc[k] >= 3 ? 3 : g.nc[k];
-    nst = nd[0] * nd[1] * nd[2];
-    if (lane < nst) {
-      int o[3] = {lane / (nd[1] * nd[2]), (lane / nd[2]) % nd[1], lane % nd[2]};
-      int w[3];
-      for (int k = 0; k < 3; ++k) {
-        int off = nd[k] == 3 ? o[k] - 1 : o[k];
-        int x = c[k] + off;
-        w[k] = x < 0 ? x + g.nc[k] : (x >= g.nc[k] ? x - g.nc[k] : x);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int n = g.nc[k];
+      nd[k] = n >= 3 ? 3 : n;
+      if (n >= 3) {
+        if (c[k] == 0) { v[k][0] = 0; v[k][1] = 1; v[k][2] = n - 1; }
+        else if (c[k] == n - 1) { v[k][0] = 0; v[k][1] = n - 2; v[k][2] = n - 1; }
+        else { v[k][0] = c[k] - 1; v[k][1] = c[k]; v[k][2] = c[k] + 1; }
+      } else {
+        v[k][0] = 0; v[k][1] = 1; v[k][2] = 2;
       }
-      my_cell = (w[0] * g.nc[1] + w[1]) * g.nc[2] + w[2];
     }
-  } else if (lane == 0) {
-    my_cell = cell;
+    nst = nd[0] * nd[1] * nd[2];
+    const int l = lane < nst ? lane : 0;
+    const int o0 = l / (nd[1] * nd[2]), o1 = (l / nd[2]) % nd[1], o2 = l % nd[2];
+    my_cell = (v[0][o0] * g.nc[1] + v[1][o1]) * g.nc[2] + v[2][o2];
   }
-  int rank = 0;
-  for (int l = 0; l < nst; ++l) {
-    int o = __shfl(my_cell, l, 64);
-    rank += (o < my_cell) ? 1 : 0;
-  }
-  if (lane < nst) s_cell[rank] = my_cell;
 
-  // centre atoms of this bin: species-major ranges of slots
+  // centre atoms of this cell (species-major ranges of slots); this wavefront
+  // takes the part-th of K equal chunks of them
   int c_lo[kMaxSpecies], c_n[kMaxSpecies];
   int n_centres = 0;
-  for (int s = 0; s < a.S; ++s) {
-    c_lo[s] = a.bin_start[s * g.n_bins + cell];
-    c_n[s] = a.bin_start[s * g.n_bins + cell + 1] - c_lo[s];
-    n_centres += c_n[s];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) {
+    c_lo[s] = 0;
+    c_n[s] = 0;
+    if (s < a.S) {
+      c_lo[s] = a.bin_start[s * g.n_bins + cell];
+      c_n[s] = a.bin_start[s * g.n_bins + cell + 1] - c_lo[s];
+      n_centres += c_n[s];
+    }
   }
+  const int chunk = (n_centres + K - 1) / K;
+  const int q0 = part * chunk, q1 = min(n_centres, q0 + chunk);
   const uint64_t lt = __lanemask_lt();
-  for (int cb = 0; cb < n_centres; cb += 64) {
-    const int nc = min(64, n_centres - cb);
+  for (int cb = q0; cb < q1; cb += 64) {
+    const int nc = min(64, q1 - cb);
     int my_i = -1;
     if (lane < nc) {
       int q = cb + lane, s = 0;
@@ -578,7 +585,6 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g)
     }
     int nr = 0, na = 0;   // lists of centre `lane`
     bool overflow = false;
-    __syncthreads();
     for (int s = 0; s < a.S; ++s) {
       if (lane < nc) {
         a.rad_off[(int64_t)my_i * (a.S + 1) + s] = nr;
@@ -586,34 +592,44 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g)
       }
       int st = 0, cnt = 0;
       if (lane < nst) {
-        int b = s * g.n_bins + s_cell[lane];
-        st = a.bin_start[b];
-        cnt = a.bin_start[b + 1] - st;
+        const int bb = s * g.n_bins + my_cell;
+        st = a.bin_start[bb];
+        cnt = a.bin_start[bb + 1] - st;
       }
       int inc = cnt;
+#pragma unroll
       for (int off = 1; off < 32; off <<= 1) {
-        int v = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += v;
+        const int u = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += u;
       }
       const int total = __shfl(inc, nst - 1, 64);
+      __syncthreads();   // previous species' readers of s_start / s_off are done
       if (lane < nst) {
         s_start[lane] = st;
         s_off[lane] = inc - cnt;
       }
       __syncthreads();
-      for (int c0 = 0; c0 < total; c0 += 64) {
-        const int c = c0 + lane;
-        int j = -1;
-        float4 pj = make_float4(0.f, 0.f, 0.f, 0.f);
+      // candidate slot and position of the lane, one block of 64 ahead
+      auto fetch = [&](int c, int& j, float4& pj) {
+        j = -1;
+        pj = make_float4(0.f, 0.f, 0.f, 0.f);
         if (c < total) {
           int lo = 0, hi = nst - 1;
           while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
+            const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
           }
           j = s_start[lo] + (c - s_off[lo]);
           pj = a.spos[j];
         }
+      };
+      int jn;
+      float4 pjn;
+      fetch(lane, jn, pjn);
+      for (int c0 = 0; c0 < total; c0 += 64) {
+        const int j = jn;
+        const float4 pj = pjn;
+        if (c0 + 64 < total) fetch(c0 + 64 + lane, jn, pjn);
         for (int ci = 0; ci < nc; ++ci) {
           const float4 pi = s_cpos[ci];
           const int i = s_cid[ci];
@@ -656,14 +672,13 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g)
           }
         }
       }
-      __syncthreads();
     }
     if (lane < nc) {
       a.rad_off[(int64_t)my_i * (a.S + 1) + a.S] = nr;
       a.ang_off[(int64_t)my_i * (a.S + 1) + a.S] = na;
       if (overflow) atomicOr(a.status, kStatusCapacity);
     }
-    __syncthreads();
+    __syncthreads();   // s_cid / s_cpos are rewritten by the next centre block
   }
 }
 
@@ -818,13 +833,15 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One wavefront per bin amortises the stencil set-up but needs enough bins
-// to fill the chip; with few bins (small boxes, one open system) work per
-// atom.  A pinned or tuned choice overrides the default.
+// Wavefronts per cell share the candidate loads and the stencil set-up among
+// a few centre atoms each; that wins on large periodic grids (98k atoms:
+// 114 us against 156 us per atom), one wavefront per atom on smaller ones
+// (12k atoms: 32 us against 36 us) and for open systems.  A pinned or tuned
+// choice overrides the default.
 int neighbour_variant(const nnp_model& m, int n) {
   if (m.geo.n_bins < 2) return 0;
   const int v = stage_variant(m, kTuneNeighbours, n);
-  return v >= 0 ? v : (m.geo.n_bins >= 2048 ? 1 : 0);
+  return v >= 0 ? v : (m.geo.periodic && m.geo.n_bins >= 2048 ? 2 : 0);
 }
 
 hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
@@ -848,8 +865,13 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   a.max_rad = m.max_rad;
   a.max_ang = m.max_ang;
   a.status = m.d_status;
-  if (neighbour_variant(m, n) == 1) {
-    hipLaunchKernelGGL(k_neighbours_cell, dim3(m.geo.n_bins), dim3(64), 0, st, a, m.geo);
+  const int v = neighbour_variant(m, n);
+  if (v >= 1) {
+    // K wavefronts share a cell, each with about 8 / 5 / 3 centre atoms
+    const int target = v == 1 ? 8 : (v == 2 ? 5 : 3);
+    const int per_bin = (n + m.geo.n_bins - 1) / m.geo.n_bins;
+    const int K = std::max(1, std::min(16, (per_bin + target - 1) / target));
+    hipLaunchKernelGGL(k_neighbours_cell, dim3((unsigned)(m.geo.n_bins * K)), dim3(64), 0, st, a, m.geo, K);
   } else {
     hipLaunchKernelGGL(k_neighbours, dim3(n), dim3(64), 0, st, a, m.geo);
   }
