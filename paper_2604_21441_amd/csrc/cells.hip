@@ -372,10 +372,15 @@ constexpr int kMaxStencil = 27;
 // by slot.  Angular neighbours (r < rc_ang) also record their position in
 // the radial list.  Lists never hold more than their capacity; an overflow
 // sets the device status word.
+// Candidates of one species per atom held in LDS (flattened stencil ranges);
+// a longer candidate sequence falls back to a binary search over the ranges.
+constexpr int kCandCap = 1024;
+
 __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
 #pragma clang fp contract(off)
-  __shared__ int s_start[kMaxSpecies][kMaxStencil];
-  __shared__ int s_off[kMaxSpecies][kMaxStencil + 1];
+  __shared__ int s_start[kMaxStencil];
+  __shared__ int s_off[kMaxStencil + 1];
+  __shared__ int s_cand[kCandCap];
   const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const float4 pi = a.spos[i];
@@ -406,30 +411,6 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
     const int o0 = l / (nd[1] * nd[2]), o1 = (l / nd[2]) % nd[1], o2 = l % nd[2];
     my_cell = (v[0][o0] * g.nc[1] + v[1][o1]) * g.nc[2] + v[2][o2];
   }
-  // candidate ranges of every species (one stencil cell per lane), prefix sums
-  int st[kMaxSpecies], total[kMaxSpecies];
-#pragma unroll
-  for (int s = 0; s < kMaxSpecies; ++s) {
-    int cnt = 0;
-    st[s] = 0;
-    if (s < a.S && lane < nst) {
-      const int b = s * g.n_bins + my_cell;
-      st[s] = a.bin_start[b];
-      cnt = a.bin_start[b + 1] - st[s];
-    }
-    int inc = cnt;
-#pragma unroll
-    for (int off = 1; off < 32; off <<= 1) {
-      const int u = __shfl_up(inc, off, 64);
-      if (lane >= off) inc += u;
-    }
-    total[s] = __shfl(inc, nst - 1, 64);
-    if (s < a.S && lane < nst) {
-      s_start[s][lane] = st[s];
-      s_off[s][lane] = inc - cnt;
-    }
-  }
-  __syncthreads();
 
   int* rad = a.rad + (int64_t)i * a.max_rad;
   int* ang = a.ang + (int64_t)i * a.max_ang;
@@ -437,15 +418,6 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   const uint64_t lt = __lanemask_lt();
   int nr = 0, na = 0;
   bool overflow = false;
-  // candidate c of species s -> slot (binary search over the range starts)
-  auto slot_of = [&](int s, int c) {
-    int lo = 0, hi = nst - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[s][mid] <= c) lo = mid; else hi = mid - 1;
-    }
-    return s_start[s][lo] + (c - s_off[s][lo]);
-  };
   auto test = [&](int j, bool& in_r, bool& in_a) {
     in_r = in_a = false;
     if (j < 0 || j == i) return;
@@ -488,23 +460,52 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
       a.rad_off[(int64_t)i * (a.S + 1) + s] = nr;
       a.ang_off[(int64_t)i * (a.S + 1) + s] = na;
     }
-    // up to two candidates per lane per step (both positions loaded before
-    // either is tested); accepted ones are appended in candidate order
-    for (int c0 = 0; c0 < total[s]; c0 += 128) {
-      const int c1 = c0 + lane, c2 = c0 + 64 + lane;
-      const int j1 = c1 < total[s] ? slot_of(s, c1) : -1;
-      bool r1, a1;
-      if (c0 + 64 < total[s]) {
-        const int j2 = c2 < total[s] ? slot_of(s, c2) : -1;
-        bool r2, a2;
-        test(j1, r1, a1);
-        test(j2, r2, a2);
-        emit(j1, r1, a1);
-        emit(j2, r2, a2);
-      } else {
-        test(j1, r1, a1);
-        emit(j1, r1, a1);
+    // candidate ranges of this species, one stencil cell per lane, and their prefix sums
+    int st = 0, cnt = 0;
+    if (lane < nst) {
+      const int b = s * g.n_bins + my_cell;
+      st = a.bin_start[b];
+      cnt = a.bin_start[b + 1] - st;
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int u = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += u;
+    }
+    const int total = __shfl(inc, nst - 1, 64);
+    // one range (an open system): slots follow directly; short per-cell ranges
+    // are flattened into LDS by their lanes; otherwise search the ranges
+    const int st0 = __shfl(st, 0, 64);
+    const bool flat = nst > 1 && total <= kCandCap;
+    __syncthreads();   // the previous species' candidates have been read
+    if (lane < nst) {
+      s_start[lane] = st;
+      s_off[lane] = inc - cnt;
+      if (flat)
+        for (int q = 0; q < cnt; ++q) s_cand[inc - cnt + q] = st + q;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      int j = -1;
+      if (c < total) {
+        if (nst == 1) {
+          j = st0 + c;
+        } else if (flat) {
+          j = s_cand[c];
+        } else {
+          int lo = 0, hi = nst - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= c) lo = mid; else hi = mid - 1;
+          }
+          j = s_start[lo] + (c - s_off[lo]);
+        }
       }
+      bool r1, a1;
+      test(j, r1, a1);
+      emit(j, r1, a1);
     }
   }
   if (lane == 0) {
