@@ -314,31 +314,48 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
   if (lane < S) count[lane * n_sys + m] = 0;   // the histogram starts from zero in the next call
   const int t0 = sys_off[m], t1 = sys_off[m + 1];
   const uint64_t lt = __lanemask_lt();
-  int base[kMaxSpecies] = {0, 0, 0, 0};
+  int base[kMaxSpecies] = {0, 0, 0, 0}, first[kMaxSpecies], cm[kMaxSpecies];
+#pragma unroll
+  for (int s = 0; s < kMaxSpecies; ++s) {   // per-system constants (wave-uniform)
+    first[s] = s < S ? bin_start[s * n_sys + m] : 0;
+    cm[s] = s < S ? cmstart[m * S + s] : 0;
+  }
+  // the next block of 64 atoms is loaded while the current one is placed
+  auto fetch = [&](int t, int& sg, int& a) {
+    sg = -1;
+    a = 0;
+    if (t < t1) {
+      sg = sigma[t];
+      a = idx[t];
+    }
+  };
+  int sg_n, a_n;
+  fetch(t0 + lane, sg_n, a_n);
   for (int c0 = t0; c0 < t1; c0 += 64) {
     const int t = c0 + lane;
     const bool ok = t < t1;
-    const int sg = ok ? sigma[t] : -1;
-    int slot = 0, rank = 0;
+    const int sg = sg_n, a = a_n;
+    const float3 p = ok ? nnp_position(pos, a, L, g) : make_float3(0.f, 0.f, 0.f);
+    if (c0 + 64 < t1) fetch(t + 64, sg_n, a_n);
+    int slot = 0, rank = 0, o = 0;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
       if (s < S) {
         const uint64_t mk = __ballot(sg == s);
         if (sg == s) {
           rank = base[s] + __popcll(mk & lt);
-          slot = bin_start[s * n_sys + m] + rank;
+          slot = first[s] + rank;
+          o = cm[s] + rank;
         }
         base[s] += __popcll(mk);
       }
     }
     if (ok) {
-      const int a = idx[t];
       perm[slot] = t;
-      order[cmstart[m * S + sg] + rank] = slot;
+      order[o] = slot;
       sbin[slot] = m;
       islot[t] = slot;
       pcount[slot] = 0;
-      const float3 p = nnp_position(pos, a, L, g);
       spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sg));
       slot_atom[slot] = a;
     }
