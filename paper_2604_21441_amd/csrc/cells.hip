@@ -1,6 +1,7 @@
-// Cell-list neighbour search: binning, a stable counting sort by
+// Cell-list neighbour search over the atoms of the index group (Methods: the
+// interface's ML subsystem): binning, a stable counting sort by
 // key = species * n_bins + bin, and per-atom neighbour lists grouped by
-// species.  A bin is a cell of the periodic box, or a whole system in batched
+// species; also the lists built from a caller's pair list.  A bin is a cell of the periodic box, or a whole system in batched
 // mode (open systems small enough for an all-pairs scan per system).
 //
 // The binning and the distance predicate are integer-exact functions of the
@@ -33,11 +34,6 @@ __device__ __forceinline__ float3 nnp_position(const float* __restrict__ pos, in
   }
   const float s = L.d / sqrtf(ux * ux + uy * uy + uz * uz);
   return make_float3(p.x + s * ux, p.y + s * uy, p.z + s * uz);
-}
-
-__global__ __launch_bounds__(kBlock) void k_fill_i32(int* __restrict__ p, int n, int v) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) p[t] = v;
 }
 
 // Bin of one position in the periodic grid.

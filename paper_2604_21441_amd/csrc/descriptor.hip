@@ -1,9 +1,14 @@
 // Symmetry-function descriptors (forward) and their adjoint (backward with
-// the FP64 force scatter).
+// the FP64 force scatter), the force gather with the energy reduction, and
+// the link-atom chain rule.  The descriptors are those of the ANI family of
+// models the paper runs and benchmarks (Methods; performance section); the
+// adjoint gives F = -grad E (Theory, eq. 2).
 //
-// Both passes run one wavefront per atom.  An output block is either the
-// radial block of one neighbour species (16 outputs) or the angular block of
-// one unordered species pair (8 x 4 outputs).
+// The forward runs one 16-lane row per atom (k_desc_fwd_rows, default) or one
+// wavefront per atom (k_desc_fwd); the adjoint one wavefront (or half of one)
+// per atom.  An output block is either the radial block of one neighbour
+// species (16 outputs) or the angular block of one unordered species pair
+// (8 x 4 outputs).
 //
 // Radial   G[s][k]   = sum_j exp(-eta_r (r - Rs_k)^2) fc(r; Rc)
 // Angular  G[p][m][n] = 2^(1-zeta) sum_{j<k} (1 + cos(theta' - theta_n))^zeta

@@ -1,5 +1,6 @@
-// Per-element networks on the matrix cores: forward (atomic energies) and the
-// hand-written backward (dE/d descriptor), fused in one kernel.
+// Per-element networks on the matrix cores: forward (atomic energies, whose
+// sum is E_ML of Theory, eq. 1) and the hand-written backward (dE/d
+// descriptor, the first link of eq. 2), fused in one kernel.
 //
 // Layout trick.  Each wavefront owns 16 atoms of one species and computes the
 // TRANSPOSED products  H_l^T [features x 16 atoms] = W_l [out x in] * H_{l-1}^T,

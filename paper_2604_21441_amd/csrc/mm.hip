@@ -1,5 +1,7 @@
 // MM point charges as an extra per-atom network input (electrostatic
-// embedding through the model, with forces on MM atoms):
+// embedding through the model, with forces on MM atoms; Methods: the 2026
+// interface passes MM positions and charges, and the model may put forces on
+// MM atoms):
 //   phi_i = ke * sum_j q_j fc(r_ij; Rm) / r_ij     over MM atoms j, r_ij < Rm
 // The pass is all-pairs over (NNP atom, MM atom): one lane per MM atom, the
 // wavefront walks the NNP atoms together and reduces each atom's sum across
