@@ -19,6 +19,7 @@ constexpr int kAngShifts = 8;    // angular radial shifts per species pair
 constexpr int kAngSects = 4;     // angle sections per species pair
 constexpr int kMaxSpecies = 4;
 constexpr int kMaxPairs = kMaxSpecies * (kMaxSpecies + 1) / 2;
+constexpr int kTileAtoms = 16;   // atoms of the smallest network tile (sizes the energy partials)
 
 // Stages with several kernel variants chosen by the autotuner.
 enum TuneStage { kTuneNeighbours = 0, kTuneDescriptor = 1, kTuneNetwork = 2, kTuneAdjoint = 3, kTuneStages = 4 };
