@@ -253,7 +253,7 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
 /*
  * Autotuner.  Several stages have more than one kernel variant (network:
  * register-resident wavefronts or row-split workgroups of 16, 32 or 64 atoms;
- * descriptor forward: a wavefront or a 16-lane row per atom; descriptor
+ * descriptor forward: a wavefront, a 16-lane or an 8-lane row per atom; descriptor
  * adjoint: a wavefront or half a wavefront per atom; neighbour search: one
  * wavefront per atom, or several per cell sharing its centre atoms).
  * nnp_autotune reruns the
@@ -282,13 +282,16 @@ typedef enum {
 /*
  * Pin the kernel variant of one stage for later calls, overriding the tuned
  * choice and the built-in default; variant = -1 removes the pin.  Variants:
- * neighbours 0 one wavefront per atom, 1 / 2 / 3 wavefronts per cell with
- * about 8 / 5 / 3 centre atoms each (with one bin, 0 is used); descriptor forward 0 one wavefront per
- * atom, 1 one 16-lane row per atom; network 0 register-resident wavefronts,
- * 1 / 2 / 3 row-split workgroups of 16 / 32 / 64 atoms (64: water-sized
- * networks only, wider ones use 32); descriptor adjoint 0 one
- * wavefront per atom, 1 half a wavefront per atom.  All variants compute the same
- * quantities (integer stages bit-identically, floating point to rounding).
+ *   neighbours: 0 one wavefront per atom; 1 / 2 / 3 wavefronts per cell with
+ *     about 8 / 5 / 3 centre atoms each (with a single bin, 0 is used);
+ *   descriptor forward: 0 one wavefront per atom; 1 / 2 one 16-lane / 8-lane
+ *     row per atom;
+ *   network: 0 register-resident wavefronts; 1 / 2 / 3 row-split workgroups
+ *     of 16 / 32 / 64 atoms (64 for water-sized networks only, wider ones
+ *     use 32);
+ *   descriptor adjoint: 0 one wavefront per atom; 1 half a wavefront per atom.
+ * All variants compute the same quantities (integer stages bit-identically,
+ * floating point to rounding).
  * Drops the cached graph.  NNP_EINVAL for an unknown stage or variant.
  */
 nnp_status nnp_set_variant(nnp_model* m, int32_t stage, int32_t variant);

@@ -284,7 +284,6 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
 // half) and the quad swaps xor 2 and xor 1; the pairings are disjoint, so
 // after four steps every lane's values cover all 16 lanes exactly once.
 
-constexpr int kRowAtoms = 16;        // atoms per 256-thread workgroup
 constexpr int kDppMirror = 0x140;
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
@@ -307,14 +306,22 @@ __device__ __forceinline__ void halve(float* v, bool upper) {
   }
 }
 
-// Sum N = 16 or 32 values over the 16 lanes of the row; lane `sub` ends with
-// totals [sub N/16, (sub+1) N/16) in v[0 .. N/16).
-template <int N>
+// Sum N values over the L = 16 or 8 lanes of a row; lane `sub` ends with
+// totals [sub N/L, (sub+1) N/L) in v[0 .. N/L).  An 8-lane row is half of a
+// DPP row, whose half-mirror pairs lanes across bit 2 within each half.
+template <int N, int L>
 __device__ __forceinline__ void row_reduce(float* v, int sub) {
-  halve<N / 2, kDppMirror>(v, sub & 8);
-  halve<N / 4, kDppHalfMirror>(v, sub & 4);
-  halve<N / 8, kDppXor2>(v, sub & 2);
-  halve<N / 16, kDppXor1>(v, sub & 1);
+  if constexpr (L == 16) {
+    halve<N / 2, kDppMirror>(v, sub & 8);
+    halve<N / 4, kDppHalfMirror>(v, sub & 4);
+    halve<N / 8, kDppXor2>(v, sub & 2);
+    halve<N / 16, kDppXor1>(v, sub & 1);
+  } else {
+    static_assert(L == 8, "row width");
+    halve<N / 2, kDppHalfMirror>(v, sub & 4);
+    halve<N / 4, kDppXor2>(v, sub & 2);
+    halve<N / 8, kDppXor1>(v, sub & 1);
+  }
 }
 
 // Start of a lane's contiguous range [r0, r1) of T unordered pairs within a
@@ -334,12 +341,15 @@ __device__ __forceinline__ void pair_start(int r0, bool same, int nB, int* j, in
   }
 }
 
+// L lanes per atom (16 or 8), 256 / L atoms per 256-thread workgroup.
+template <int L>
 __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, Geometry geo) {
+  constexpr int kAtoms = 256 / L;
   extern __shared__ float4 smem_r[];
-  const int row = threadIdx.x >> 4, sub = threadIdx.x & 15;
+  const int row = threadIdx.x / L, sub = threadIdx.x % L;
   float4* G = smem_r + row * a.max_ang;                                      // (u, r hq)
-  float* W = reinterpret_cast<float*>(smem_r + kRowAtoms * a.max_ang) + row * a.max_ang;  // fc sq_pref
-  const int li = xcd_block(blockIdx.x, gridDim.x) * kRowAtoms + row;   // place in the visiting order
+  float* W = reinterpret_cast<float*>(smem_r + kAtoms * a.max_ang) + row * a.max_ang;  // fc sq_pref
+  const int li = xcd_block(blockIdx.x, gridDim.x) * kAtoms + row;   // place in the visiting order
   const bool valid = li < a.n;
   const Consts c = make_consts(p);
   const int S1 = p.S + 1;
@@ -353,7 +363,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
 
   // angular neighbour geometry of this row's atom
   const int na = valid ? aoff[p.S] : 0;
-  for (int u = sub; u < na; u += 16) {
+  for (int u = sub; u < na; u += L) {
     Geo d = displacement(pi, a.spos[arow[u]], geo);
     G[u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
     W[u] = (0.5f * cos_rev(d.r * c.inv2rca) + 0.5f) * p.sq_pref;
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
 #pragma unroll
     for (int k = 0; k < kRadShifts; ++k) acc[k] = 0.f;
     const int t1 = valid ? roff[s + 1] : 0;
-    for (int t = (valid ? roff[s] : 0) + sub; t < t1; t += 16) {
+    for (int t = (valid ? roff[s] : 0) + sub; t < t1; t += L) {
 #pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
       Geo d = displacement(pi, a.spos[rrow[t]], geo);
       const float fc = fmaf(0.5f, cos_rev(d.r * c.inv2rc), 0.5f);
@@ -376,8 +386,11 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
         acc[k] = fmaf(ex2(-(tt * tt)), fc, acc[k]);
       }
     }
-    row_reduce<kRadShifts>(acc, sub);
-    if (valid) xo[s * kRadShifts + sub] = acc[0];
+    row_reduce<kRadShifts, L>(acc, sub);
+    if (valid) {
+      if constexpr (L == 16) xo[s * kRadShifts + sub] = acc[0];
+      else *reinterpret_cast<float2*>(xo + s * kRadShifts + 2 * sub) = make_float2(acc[0], acc[1]);
+    }
   }
   __syncthreads();
 
@@ -393,7 +406,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
       nB = aoff[sb + 1] - ob;
     }
     const int T = same ? nA * (nA - 1) / 2 : nA * nB;
-    const int r0 = (T * sub) >> 4, r1 = (T * (sub + 1)) >> 4;
+    const int r0 = (T * sub) / L, r1 = (T * (sub + 1)) / L;
     float acc[kAngShifts * kAngSects];
 #pragma unroll
     for (int e = 0; e < kAngShifts * kAngSects; ++e) acc[e] = 0.f;
@@ -428,10 +441,14 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
         }
       }
     }
-    row_reduce<kAngShifts * kAngSects>(acc, sub);
-    if (valid)
-      *reinterpret_cast<float2*>(xo + p.S * kRadShifts + q * kAngShifts * kAngSects + 2 * sub) =
-          make_float2(acc[0], acc[1]);
+    row_reduce<kAngShifts * kAngSects, L>(acc, sub);
+    if (valid) {
+      float* dst = xo + p.S * kRadShifts + q * kAngShifts * kAngSects;
+      if constexpr (L == 16)
+        *reinterpret_cast<float2*>(dst + 2 * sub) = make_float2(acc[0], acc[1]);
+      else
+        *reinterpret_cast<float4*>(dst + 4 * sub) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
   }
 }
 
@@ -817,7 +834,8 @@ hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forc
 }
 
 // Forward descriptor variants: 0 = one wavefront per atom, 1 = one 16-lane
-// row per atom (default).
+// row per atom (default), 2 = one 8-lane row per atom (fewer idle lanes,
+// half the wavefronts: for large systems).
 int descriptor_variant(const nnp_model& m, int n) {
   const int v = stage_variant(m, kTuneDescriptor, n);
   return v >= 0 ? v : 1;
@@ -836,10 +854,13 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   a.max_ang = m.max_ang;
   a.n = n;
   a.x = m.d_x;
-  if (descriptor_variant(m, n) == 1) {
-    const size_t lds = (sizeof(float4) + sizeof(float)) * kRowAtoms * (size_t)m.max_ang;
-    hipLaunchKernelGGL(k_desc_fwd_rows, dim3((n + kRowAtoms - 1) / kRowAtoms), dim3(256), lds, st, a, m.dp,
-                       m.geo);
+  const int v = descriptor_variant(m, n);
+  if (v == 1) {
+    const size_t lds = (sizeof(float4) + sizeof(float)) * 16 * (size_t)m.max_ang;
+    hipLaunchKernelGGL(k_desc_fwd_rows<16>, dim3((n + 15) / 16), dim3(256), lds, st, a, m.dp, m.geo);
+  } else if (v == 2) {
+    const size_t lds = (sizeof(float4) + sizeof(float)) * 32 * (size_t)m.max_ang;
+    hipLaunchKernelGGL(k_desc_fwd_rows<8>, dim3((n + 31) / 32), dim3(256), lds, st, a, m.dp, m.geo);
   } else {
     const size_t lds = sizeof(float) * (64 * (size_t)kPartStride + 5 * (size_t)m.max_ang);
     hipLaunchKernelGGL(k_desc_fwd, dim3(n), dim3(64), lds, st, a, m.dp, m.geo);

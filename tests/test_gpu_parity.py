@@ -286,7 +286,7 @@ def test_autotune_keeps_results(P, w_water):
         E0, F0 = E0.clone(), F0.clone()
         chosen = m.autotune(3)
         assert chosen["network"] in (0, 1, 2, 3) and chosen["neighbours"] in (0, 1, 2, 3)
-        assert chosen["descriptor"] in (0, 1) and chosen["adjoint"] in (0, 1)
+        assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1)
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
         assert m.status() == 0
@@ -297,7 +297,7 @@ def test_autotune_keeps_results(P, w_water):
 
 
 VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours", 2, "fp32"),
-            ("neighbours", 3, "fp32"), ("descriptor", 0, "fp32"),
+            ("neighbours", 3, "fp32"), ("descriptor", 0, "fp32"), ("descriptor", 2, "fp32"),
             ("descriptor", 1, "fp32"), ("network", 0, "fp32"), ("network", 1, "fp32"), ("network", 2, "fp32"),
             ("network", 3, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
             ("network", 3, "bf16"), ("adjoint", 0, "fp32"),
@@ -325,7 +325,8 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    for bad in ((stage, 4 if stage in ("network", "neighbours") else 2), (4, 0), (stage, -2)):
+    nvar = {"network": 4, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
+    for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
         assert ex.value.status == P._lib.NNP_EINVAL
