@@ -100,11 +100,12 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
         nv = v.get("network", 2)
         dims = f"{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {bf}"
         cols = {1: 1, 2: 2, 3: 4 if k0 <= 128 else 2}.get(nv)
+        if nv == 4:
+            return f"k_mlp_mixed<{dims}>"
         return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {cols}>"
     if stage == "adjoint":
         return ["k_desc_bwd<64>", "k_desc_bwd<32>"][v.get("adjoint", 0)]
-    return {"gather": "k_force_gather",
-            "energy": "k_energy_final" if periodic else "k_energy"}.get(stage)
+    return {"gather": "k_force_gather", "energy": "k_force_gather"}.get(stage)
 
 
 def profile_traffic(workload, kernel):

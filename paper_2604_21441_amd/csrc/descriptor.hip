@@ -707,6 +707,7 @@ struct EnergyArgs {
   const float* e;          // atomic energies in sorted order
   const int* bin_start;    // species buckets [s * n_bins, (s + 1) * n_bins)
   int n_bins, S, tile_rows;
+  int mixed;               // the network's narrow species used 16-atom tiles
   int empty;               // no atoms: the energies are zero (the buckets are not read)
   double* out;
   int accumulate;
@@ -718,9 +719,12 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int sys) {
   double acc = 0.0;
   if (ea.empty) {
   } else if (ea.part != nullptr) {
+    const int narrow = ea.mixed ? narrow_species(ea.bin_start, ea.S, ea.n_bins) : -1;
     int tiles = 0;
-    for (int s = 0; s < ea.S; ++s)
-      tiles += (ea.bin_start[(s + 1) * ea.n_bins] - ea.bin_start[s * ea.n_bins] + ea.tile_rows - 1) / ea.tile_rows;
+    for (int s = 0; s < ea.S; ++s) {
+      const int rows = s == narrow ? 16 : ea.tile_rows;
+      tiles += (ea.bin_start[(s + 1) * ea.n_bins] - ea.bin_start[s * ea.n_bins] + rows - 1) / rows;
+    }
     for (int t = threadIdx.x; t < tiles; t += kBlock) acc += ea.part[t];
   } else {
     for (int s = 0; s < ea.S; ++s) {
@@ -910,6 +914,7 @@ hipError_t launch_force_gather(nnp_model& m, int n, double* forces, int assign, 
   ea.n_bins = m.geo.n_bins;
   ea.S = m.S;
   ea.tile_rows = 16 * m.mlp_cols;
+  ea.mixed = m.mlp_mixed;
   ea.empty = n == 0;
   ea.out = energies;
   ea.accumulate = accumulate;

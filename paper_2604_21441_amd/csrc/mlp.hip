@@ -140,7 +140,7 @@ struct Own {  // number of row tiles r = w + 4 j owned by one wavefront
 // out[j][c] = A-rows (w + 4 j) of W [R x K] times the K/16 LDS tiles `in[c][kb]`.
 template <int R, int K, bool BF16, int C>
 __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* in, int in_tiles, v4f (*out)[C],
-                                         int w, int lane) {
+                                         int w, int lane, int cw) {
   constexpr int NJ = Own<R>::n;
   constexpr int KB = BF16 ? K / 32 : K / 16;
   constexpr int kPrefetch = PrefetchDepth<BF16, (16 * R > 160 || K > 160)>::value;
@@ -166,6 +166,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
     F bv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      if (c >= cw) continue;   // a narrow tile (workgroup-uniform)
       if constexpr (BF16)
         bv[c] = to_bf16x8(in[(c * in_tiles + 2 * kb) * 64 + lane], in[(c * in_tiles + 2 * kb + 1) * 64 + lane]);
       else
@@ -176,14 +177,15 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
       const int r = w + kWaves * j;
       if (r < R) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) out[j][c] = mma(cur[j], bv[c], out[j][c]);
+        for (int c = 0; c < C; ++c)
+          if (c < cw) out[j][c] = mma(cur[j], bv[c], out[j][c]);
       }
     }
   }
 }
 
-template <int K0, int N1, int N2, int N3, bool BF16, int C>
-__global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a, float alpha) {
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED>
+__device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
   constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
   constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
@@ -199,15 +201,19 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
   const int q = lane >> 4;
   const int col = lane & 15;
 
-  // workgroup -> (species, tile of 16*C rows)
-  int s = -1, row0 = 0, row_end = 0, before = 0;
+  // workgroup -> (species, tile of 16*cw rows); cw = C except for the narrow
+  // species of the mixed tiling
+  const int narrow = MIXED ? narrow_species(a.bin_start, a.S, a.n_bins) : -1;
+  int s = -1, row0 = 0, row_end = 0, before = 0, cw = C;
   for (int ss = 0; ss < a.S; ++ss) {
-    int b0 = a.bin_start[ss * a.n_bins], b1 = a.bin_start[(ss + 1) * a.n_bins];
-    int nt = (b1 - b0 + 16 * C - 1) / (16 * C);
+    const int b0 = a.bin_start[ss * a.n_bins], b1 = a.bin_start[(ss + 1) * a.n_bins];
+    const int width = ss == narrow ? 1 : C;
+    const int nt = (b1 - b0 + 16 * width - 1) / (16 * width);
     if ((int)blockIdx.x < before + nt) {
       s = ss;
-      row0 = b0 + ((int)blockIdx.x - before) * 16 * C;
-      row_end = b1;
+      cw = width;
+      row0 = b0 + ((int)blockIdx.x - before) * 16 * width;
+      row_end = min(b1, row0 + 16 * width);
       break;
     }
     before += nt;
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
 #pragma unroll
       for (int c = 0; c < C; ++c) h1[j][c] = bias;
     }
-    gemm_lds<N1 / 16, K0, BF16, C>(Wm + oF1, bufX, TX, h1, w, lane);
+    gemm_lds<N1 / 16, K0, BF16, C>(Wm + oF1, bufX, TX, h1, w, lane, cw);
 #pragma unroll
     for (int j = 0; j < Own<N1>::n; ++j) {
       const int r = w + kWaves * j;
@@ -268,7 +274,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
 #pragma unroll
       for (int c = 0; c < C; ++c) h2[j][c] = bias;
     }
-    gemm_lds<N2 / 16, N1, BF16, C>(Wm + oF2, bufA, TA, h2, w, lane);
+    gemm_lds<N2 / 16, N1, BF16, C>(Wm + oF2, bufA, TA, h2, w, lane, cw);
     __syncthreads();   // everyone has read A (h1) and X (x) before X is overwritten
 #pragma unroll
     for (int j = 0; j < Own<N2>::n; ++j) {
@@ -293,7 +299,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
 #pragma unroll
       for (int c = 0; c < C; ++c) h3[j][c] = bias;
     }
-    gemm_lds<N3 / 16, N2, BF16, C>(Wm + oF3, bufX, TX, h3, w, lane);
+    gemm_lds<N3 / 16, N2, BF16, C>(Wm + oF3, bufX, TX, h3, w, lane, cw);
     float ep[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) ep[c] = 0.f;
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
     for (int j = 0; j < Own<N2>::n; ++j)
 #pragma unroll
       for (int c = 0; c < C; ++c) d2[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    gemm_lds<N2 / 16, N3, BF16, C>(Wm + oB3, bufA, TA, d2, w, lane);
+    gemm_lds<N2 / 16, N3, BF16, C>(Wm + oB3, bufA, TA, d2, w, lane, cw);
 #pragma unroll
     for (int j = 0; j < Own<N2>::n; ++j) {
       const int r = w + kWaves * j;
@@ -357,7 +363,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
     for (int j = 0; j < Own<N1>::n; ++j)
 #pragma unroll
       for (int c = 0; c < C; ++c) d1[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    gemm_lds<N1 / 16, N2, BF16, C>(Wm + oB2, bufX, TX, d1, w, lane);
+    gemm_lds<N1 / 16, N2, BF16, C>(Wm + oB2, bufX, TX, d1, w, lane, cw);
 #pragma unroll
     for (int j = 0; j < Own<N1>::n; ++j) {
       const int r = w + kWaves * j;
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
       for (int j = 0; j < Own<K0 / 16>::n; ++j)
 #pragma unroll
         for (int c = 0; c < C; ++c) gx[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-      gemm_lds<K0 / 16, N1, BF16, C>(Wm + oB1, bufA, TA, gx, w, lane);
+      gemm_lds<K0 / 16, N1, BF16, C>(Wm + oB1, bufA, TA, gx, w, lane, cw);
 #pragma unroll
       for (int j = 0; j < Own<K0 / 16>::n; ++j) {
         const int r = w + kWaves * j;
@@ -420,6 +426,21 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
       if (lane == 0) a.part[blockIdx.x] = ev;
     }
   }
+}
+
+template <int K0, int N1, int N2, int N3, bool BF16, int C>
+__global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a, float alpha) {
+  mlp_split_body<K0, N1, N2, N3, BF16, C, false>(a, alpha);
+}
+
+// Mixed tiling: tiles of 32 atoms, of 16 for the species with the fewest
+// atoms.  For a small system the workgroups then come in two sizes whose
+// count matches the CUs better than one size does (water, 4,096 molecules:
+// 256 + 256 instead of 384 tiles).  Every atom's arithmetic is the same as
+// in the uniform tiling.
+template <int K0, int N1, int N2, int N3, bool BF16>
+__global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_mixed(MlpArgs a, float alpha) {
+  mlp_split_body<K0, N1, N2, N3, BF16, 2, true>(a, alpha);
 }
 
 // Register-resident variant: each wavefront owns 16 atoms and keeps the whole
@@ -608,6 +629,10 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
     const int64_t waves = (n + 15) / 16 + m.S;
     hipLaunchKernelGGL((k_mlp_reg<K0, N1, N2, N3, BF16>), dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, a, m.celu_alpha);
+  } else if (variant == 4) {   // row split, 32 atoms per workgroup, 16 for the smallest species
+    const int64_t tiles = (n + 15) / 16 + m.S;
+    hipLaunchKernelGGL((k_mlp_mixed<K0, N1, N2, N3, BF16>), dim3((unsigned)tiles), dim3(256), 0, st, a,
+                       m.celu_alpha);
   } else if (variant == 3 && K0 <= 128) {   // row split, 64 atoms per workgroup (narrow networks)
     if constexpr (K0 <= 128) {
       const int64_t tiles = (n + 63) / 64 + m.S;
@@ -658,7 +683,8 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
   const int v = mlp_variant(m, n);
-  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 ? 2 : 1);
+  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 ? 2 : 1);
+  m.mlp_mixed = v == 4;
   switch (m.net_kind) {
     case 0:
       return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, v, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, v, st);

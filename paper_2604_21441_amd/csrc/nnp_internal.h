@@ -35,6 +35,24 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Mixed network tiling: the species with the fewest atoms (lowest index on
+// ties; empty species are skipped) takes tiles of 16 atoms, the others the
+// kernel's full width, so that a small system splits into workgroups of more
+// even size.  -1 when there is a single species.  The network kernel and the energy reduction both call it
+// on the same bucket boundaries, so they agree on the tile count.
+__device__ __forceinline__ int narrow_species(const int* bin_start, int S, int n_bins) {
+  if (S < 2) return -1;
+  int best = -1, fewest = 0x7fffffff;
+  for (int s = 0; s < S; ++s) {
+    const int c = bin_start[(s + 1) * n_bins] - bin_start[s * n_bins];
+    if (c > 0 && c < fewest) {
+      fewest = c;
+      best = s;
+    }
+  }
+  return best;
+}
+
 // Device status bits.
 constexpr int kStatusCapacity = 1;
 constexpr int kStatusNonFinite = 2;
@@ -114,6 +132,7 @@ struct nnp_model {
   float celu_alpha = 0.1f;
   nnp::DescParams dp{};
   int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
+  int mlp_mixed = 0;                    // the species with the fewest atoms uses one column tile
   std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
   int force_variant[nnp::kTuneStages] = {-1, -1, -1, -1};   // set while timing candidates
   int pinned[nnp::kTuneStages] = {-1, -1, -1, -1};          // nnp_set_variant
@@ -207,7 +226,7 @@ int adjoint_variant(const nnp_model& m, int n);
 // Variant of a tuned stage: the candidate being timed, else the pinned one,
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
-constexpr int kStageVariants[kTuneStages] = {4, 3, 4, 2};
+constexpr int kStageVariants[kTuneStages] = {4, 3, 5, 2};
 int size_bucket(int n);
 
 // error helpers (api.cpp)

@@ -285,7 +285,7 @@ def test_autotune_keeps_results(P, w_water):
         torch.cuda.synchronize()
         E0, F0 = E0.clone(), F0.clone()
         chosen = m.autotune(3)
-        assert chosen["network"] in (0, 1, 2, 3) and chosen["neighbours"] in (0, 1, 2, 3)
+        assert chosen["network"] in (0, 1, 2, 3, 4) and chosen["neighbours"] in (0, 1, 2, 3)
         assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1)
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
@@ -299,8 +299,8 @@ def test_autotune_keeps_results(P, w_water):
 VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours", 2, "fp32"),
             ("neighbours", 3, "fp32"), ("descriptor", 0, "fp32"), ("descriptor", 2, "fp32"),
             ("descriptor", 1, "fp32"), ("network", 0, "fp32"), ("network", 1, "fp32"), ("network", 2, "fp32"),
-            ("network", 3, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
-            ("network", 3, "bf16"), ("adjoint", 0, "fp32"),
+            ("network", 3, "fp32"), ("network", 4, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"),
+            ("network", 2, "bf16"), ("network", 3, "bf16"), ("network", 4, "bf16"), ("adjoint", 0, "fp32"),
             ("adjoint", 1, "fp32")]
 
 
@@ -325,13 +325,44 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    nvar = {"network": 4, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
+    nvar = {"network": 5, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
     for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
         assert ex.value.status == P._lib.NNP_EINVAL
     m.set_variant(stage, -1)
     m.close()
+
+
+def test_mixed_network_tiling_bit_identical(P, w_water, w_hcno, boxes):
+    """The mixed tiling (16-atom tiles for the species with the fewest atoms)
+    changes only which workgroup computes an atom: every atom's network output
+    and hence every force is bit-identical to the uniform 32-atom tiling, and
+    the energy differs at most by the FP64 summation order of the partials."""
+    pos, Z, box = boxes["c2"]
+    out = {}
+    for v in (2, 4):
+        m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+        m.set_variant("network", v)
+        out[v] = _run(m, pos, Z, box)
+        assert m.variants()["network"] == v
+        m.close()
+    assert np.array_equal(out[2][1], out[4][1])
+    assert abs(out[2][0][0] - out[4][0][0]) <= 1e-12 * abs(out[2][0][0])
+    # batched open systems (per-system energies summed from the atomic ones)
+    pos, Z, off = sy.walk_batch(12, seed=5)
+    d = torch.from_numpy(pos).cuda()
+    res = {}
+    for v in (2, 4):
+        m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="bf16")
+        m.set_variant("network", v)
+        E, F = m.compute_batch(d, Z, off)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        res[v] = (E.cpu().numpy(), F.cpu().numpy())
+        m.close()
+    assert np.array_equal(res[2][0], res[4][0])
+    assert np.array_equal(res[2][1], res[4][1])
 
 
 def test_neighbour_sets_batched_and_open(P, w_hcno):
