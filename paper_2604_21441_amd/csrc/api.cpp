@@ -417,7 +417,7 @@ nnp_status setup_periodic(nnp_model* m, const float* box) {
     g.box[k] = L;
     g.inv_box[k] = 1.0f / L;
     float q = std::floor(L / rc);
-    g.nc[k] = q < 1.f ? 1 : (int)q;
+    g.nc[k] = q < 1.f ? 1 : (q > (float)kMaxCellsPerDim ? kMaxCellsPerDim : (int)q);
     cells *= g.nc[k];
   }
   // keep the grid within the reserved bins (larger cells stay correct)
@@ -429,7 +429,10 @@ nnp_status setup_periodic(nnp_model* m, const float* box) {
     g.nc[k] = g.nc[k] > 1 ? g.nc[k] / 2 : 1;
     cells = (long long)g.nc[0] * g.nc[1] * g.nc[2];
   }
-  for (int k = 0; k < 3; ++k) g.cell_scale[k] = (float)g.nc[k] * g.inv_box[k];
+  for (int k = 0; k < 3; ++k) {
+    g.cell_scale[k] = (float)g.nc[k] * g.inv_box[k];
+    g.cell_len[k] = g.box[k] / (float)g.nc[k];
+  }
   g.n_bins = (int)cells;
   return NNP_OK;
 }

@@ -274,6 +274,9 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
   int b0 = start[wave], b1 = start[wave + 1];
   const int sp = wave / g.n_bins, bin = wave - sp * g.n_bins;
   const int o0 = cmstart[bin * S + sp];
+  // the cell's coordinates, packed for the neighbour search
+  const int cz = bin % g.nc[2], cxy = bin / g.nc[2];
+  const int packed = ((cxy / g.nc[1]) << 20) | ((cxy % g.nc[1]) << 10) | cz;
   for (int e = b0 + lane; e < b1; e += 64) {
     int t = tmp[e];
     int rank = 0;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
     int slot = b0 + rank;
     perm[slot] = t;
     order[o0 + rank] = slot;
-    sbin[slot] = bin;
+    sbin[slot] = packed;
     islot[t] = slot;
     pcount[slot] = 0;
     const int a = idx[t];
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(64) void k_rank_systems(const int* __restrict__ sys
 
 struct NeighArgs {
   const int* order;        // bin-major visiting order of the slots
-  const int* sbin;         // bin of each slot
+  const int* sbin;         // packed cell coordinates (periodic) or system of each slot
   const float4* spos;
   const int* perm;
   const int* key;
@@ -388,6 +391,11 @@ constexpr int kMaxStencil = 27;
 // Candidates of one species per atom held in LDS (flattened stencil ranges);
 // a longer candidate sequence falls back to a binary search over the ranges.
 constexpr int kCandCap = 1024;
+// Distance (A) added to the cutoff before a stencil cell is skipped.  Cell
+// assignment and the distance test round positions to a few FP32 ulps,
+// about 1e-3 A for coordinates of 10^4 A, so skipping is exact for inputs
+// within many box lengths of the origin.
+constexpr float kCullMargin = 0.02f;
 
 __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
 #pragma clang fp contract(off)
@@ -397,32 +405,53 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   const int i = a.order[xcd_block(blockIdx.x, gridDim.x)];
   const int lane = threadIdx.x;
   const float4 pi = a.spos[i];
-  const int bin = a.sbin[i];
-  // Stencil cells in ascending id order: per dimension the (wrapped) offsets
-  // are sorted, and ids are lexicographic in (x, y, z).
+  const int sb = a.sbin[i];
+  // Stencil cells in ascending id order: per dimension the (wrapped)
+  // coordinates {c-1, c, c+1} are sorted, and ids are lexicographic in
+  // (x, y, z).  Lane l < nst takes the l-th of them.
   int nst = 1;
-  int my_cell = bin;
+  int my_cell = sb;   // open systems: the system's bin
+  bool culled = false;
   if (g.periodic) {
-    int c[3], nd[3], v[3][3];
-    c[0] = bin / (g.nc[1] * g.nc[2]);
-    c[1] = (bin / g.nc[2]) % g.nc[1];
-    c[2] = bin % g.nc[2];
+    const int c[3] = {sb >> 20, (sb >> 10) & 1023, sb & 1023};
+    int nd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nd[k] = g.nc[k] >= 3 ? 3 : g.nc[k];
+    nst = nd[0] * nd[1] * nd[2];
+    const int l = lane < nst ? lane : 0;
+    int o[3];
+    if (nst == 27) {
+      o[0] = l / 9; o[1] = (l / 3) % 3; o[2] = l % 3;
+    } else {
+      o[0] = l / (nd[1] * nd[2]); o[1] = (l / nd[2]) % nd[1]; o[2] = l % nd[2];
+    }
+    // A stencil cell whose nearest point lies beyond the cutoff (plus
+    // kCullMargin) holds no neighbour of this centre: its lane offers no
+    // candidates.  The gap per dimension is the centre's offset inside its
+    // own cell (lower neighbour) or the rest of the cell (upper neighbour).
+    const float pc[3] = {pi.x, pi.y, pi.z};
+    float gap2 = 0.f;
+    int v[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int n = g.nc[k];
-      nd[k] = n >= 3 ? 3 : n;
-      if (n >= 3) {        // {c-1, c, c+1} wrapped, ascending
-        if (c[k] == 0) { v[k][0] = 0; v[k][1] = 1; v[k][2] = n - 1; }
-        else if (c[k] == n - 1) { v[k][0] = 0; v[k][1] = n - 2; v[k][2] = n - 1; }
-        else { v[k][0] = c[k] - 1; v[k][1] = c[k]; v[k][2] = c[k] + 1; }
-      } else {             // every cell of the dimension
-        v[k][0] = 0; v[k][1] = 1; v[k][2] = 2;
+      if (n < 3) {   // every cell of the dimension is in the stencil
+        v[k] = o[k];
+        continue;
       }
+      // offset of the o-th sorted coordinate: c = 0 gives {0, 1, n-1},
+      // c = n-1 gives {0, n-2, n-1}, otherwise {c-1, c, c+1}
+      const int d = c[k] == 0 ? (o[k] == 2 ? -1 : o[k]) : (c[k] == n - 1 ? (o[k] == 0 ? 1 : o[k] - 2) : o[k] - 1);
+      const int w = c[k] + d;
+      v[k] = w < 0 ? w + n : (w >= n ? w - n : w);
+      const float x = pc[k] - floorf(pc[k] * g.inv_box[k]) * g.box[k];
+      const float u = x - (float)c[k] * g.cell_len[k];
+      const float gap = d == 0 ? 0.f : fmaxf(d > 0 ? g.cell_len[k] - u : u, 0.f);
+      gap2 += gap * gap;
     }
-    nst = nd[0] * nd[1] * nd[2];
-    const int l = lane < nst ? lane : 0;
-    const int o0 = l / (nd[1] * nd[2]), o1 = (l / nd[2]) % nd[1], o2 = l % nd[2];
-    my_cell = (v[0][o0] * g.nc[1] + v[1][o1]) * g.nc[2] + v[2][o2];
+    my_cell = (v[0] * g.nc[1] + v[1]) * g.nc[2] + v[2];
+    const float rm = sqrtf(a.rc2) + kCullMargin;
+    culled = gap2 > rm * rm;
   }
 
   int* rad = a.rad + (int64_t)i * a.max_rad;
@@ -475,7 +504,7 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
     }
     // candidate ranges of this species, one stencil cell per lane, and their prefix sums
     int st = 0, cnt = 0;
-    if (lane < nst) {
+    if (lane < nst && !culled) {
       const int b = s * g.n_bins + my_cell;
       st = a.bin_start[b];
       cnt = a.bin_start[b + 1] - st;
@@ -855,7 +884,7 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
 int neighbour_variant(const nnp_model& m, int n) {
   if (m.geo.n_bins < 2) return 0;
   const int v = stage_variant(m, kTuneNeighbours, n);
-  return v >= 0 ? v : (m.geo.periodic && m.geo.n_bins >= 2048 ? 2 : 0);
+  return v >= 0 ? v : 0;
 }
 
 hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {

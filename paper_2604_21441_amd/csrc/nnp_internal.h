@@ -85,8 +85,12 @@ struct Geometry {
   float box[3], inv_box[3];
   int nc[3];                            // cells per dimension (periodic)
   float cell_scale[3];                  // nc * (1/L) in FP32
+  float cell_len[3];                    // L / nc in FP32
   int n_bins;                           // cells (periodic) or systems (batched)
 };
+// Cells per dimension are capped so that a cell's coordinates pack into
+// 10 bits each (larger cells stay correct).
+constexpr int kMaxCellsPerDim = 1023;
 
 // Link atoms: NNP-local atoms t >= n_group have idx[t] = -1 - l.
 struct LinkArgs {
@@ -162,7 +166,7 @@ struct nnp_model {
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
   float4* d_spos = nullptr;    // slot -> position (w = species bits)
   int* d_slot_atom = nullptr;  // slot -> atom index
-  int* d_sbin = nullptr;       // slot -> bin (cell or system)
+  int* d_sbin = nullptr;       // slot -> cell coordinates x<<20 | y<<10 | z (periodic) or system
   int* d_loc = nullptr;        // system atom -> NNP-local index or -1 (pair lists)
   int* d_islot = nullptr;      // NNP-local index -> slot
   int* d_pcount = nullptr;     // radial entries per slot while a pair list is scattered

@@ -57,7 +57,12 @@ def water_models(P, w_water):
 @pytest.fixture(scope="module")
 def boxes():
     # "large" (18,432 atoms) adds a box of several scan chunks per species
-    return {"c1": sy.water_box(64, 12.42, seed=0), "c2": sy.water_box(4096, 49.7, seed=0),
+    c2 = sy.water_box(4096, 49.7, seed=0)
+    # "c2s": the same box with every atom moved by whole box lengths (-3..3 per
+    # component), so that positions lie far outside [0, L)
+    k = np.random.default_rng(3).integers(-3, 4, size=c2[0].shape)
+    c2s = ((c2[0] + k * np.asarray(c2[2])).astype(c2[0].dtype), c2[1], c2[2])
+    return {"c1": sy.water_box(64, 12.42, seed=0), "c2": c2, "c2s": c2s,
             "large": sy.water_box(6144, 56.9, seed=0)}
 
 
@@ -97,7 +102,7 @@ def test_cell_list_bit_exact(P, water_models, boxes, name):
     assert np.array_equal(m.read(P._lib.NNP_BUF_ORDER), expect)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c2s", "large"])
 def test_neighbour_sets_bit_exact(P, water_models, boxes, name):
     pos, Z, box = boxes[name]
     m = water_models["fp32"]
