@@ -457,45 +457,12 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   int* rad = a.rad + (int64_t)i * a.max_rad;
   int* ang = a.ang + (int64_t)i * a.max_ang;
   int* angpos = a.angpos + (int64_t)i * a.max_ang;
-  const uint64_t lt = __lanemask_lt();
-  int nr = 0, na = 0;
+  int nr = 0, na = 0;   // list lengths so far (wavefront-uniform)
   bool overflow = false;
-  auto test = [&](int j, bool& in_r, bool& in_a) {
-    in_r = in_a = false;
-    if (j < 0 || j == i) return;
-    const float4 pj = a.spos[j];
-    float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    if (g.periodic) {
-      float sx = rintf(dx * g.inv_box[0]);
-      float sy = rintf(dy * g.inv_box[1]);
-      float sz = rintf(dz * g.inv_box[2]);
-      float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-      dx = dx - tx; dy = dy - ty; dz = dz - tz;
-    }
-    float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-    float r2 = xx + yy;
-    r2 = r2 + zz;
-    in_r = r2 < a.rc2;
-    in_a = r2 < a.rca2;
-  };
-  auto emit = [&](int j, bool in_r, bool in_a) {
-    const uint64_t mr = __ballot(in_r);
-    const int pr = nr + __popcll(mr & lt);
-    const bool in_a2 = in_a && pr < a.max_rad;   // angular entries point into the radial list
-    const uint64_t ma = __ballot(in_a2);
-    const int pa = na + __popcll(ma & lt);
-    if (in_r && pr < a.max_rad) rad[pr] = j;
-    if (in_a2 && pa < a.max_ang) {
-      ang[pa] = j;
-      angpos[pa] = pr;
-    }
-    nr += __popcll(mr);
-    na += __popcll(ma);
-    if (nr > a.max_rad || na > a.max_ang) {
-      overflow = true;
-      nr = min(nr, a.max_rad);
-      na = min(na, a.max_ang);
-    }
+  // Accepted candidates are appended in lane order: a lane's place is the
+  // number of accepting lanes below it.
+  auto below = [](uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
   };
   for (int s = 0; s < a.S; ++s) {
     if (lane == 0) {
@@ -515,10 +482,10 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
       const int u = __shfl_up(inc, off, 64);
       if (lane >= off) inc += u;
     }
-    const int total = __shfl(inc, nst - 1, 64);
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, nst - 1, 64));
     // one range (an open system): slots follow directly; short per-cell ranges
     // are flattened into LDS by their lanes; otherwise search the ranges
-    const int st0 = __shfl(st, 0, 64);
+    const int st0 = __builtin_amdgcn_readfirstlane(st);
     const bool flat = nst > 1 && total <= kCandCap;
     __syncthreads();   // the previous species' candidates have been read
     if (lane < nst) {
@@ -528,8 +495,8 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
         for (int q = 0; q < cnt; ++q) s_cand[inc - cnt + q] = st + q;
     }
     __syncthreads();
-    for (int c0 = 0; c0 < total; c0 += 64) {
-      const int c = c0 + lane;
+    // candidate slot at position c of the flattened sequence (-1 beyond it)
+    auto candidate = [&](int c) {
       int j = -1;
       if (c < total) {
         if (nst == 1) {
@@ -545,9 +512,50 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
           j = s_start[lo] + (c - s_off[lo]);
         }
       }
-      bool r1, a1;
-      test(j, r1, a1);
-      emit(j, r1, a1);
+      return j;
+    };
+    // the next step's candidate and position are fetched before this step's
+    // test, so the load is in flight while the wavefront works
+    int j = candidate(lane);
+    float4 pj = a.spos[j >= 0 && j != i ? j : i];
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int jn = candidate(c0 + 64 + lane);
+      const float4 pn = a.spos[jn >= 0 && jn != i ? jn : i];
+      // straight-line test (invalid lanes read the centre's own position and
+      // are masked), so the ballots take the comparison masks directly
+      const bool valid = j >= 0 && j != i;
+      float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+      if (g.periodic) {
+        float sx = rintf(dx * g.inv_box[0]);
+        float sy = rintf(dy * g.inv_box[1]);
+        float sz = rintf(dz * g.inv_box[2]);
+        float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
+        dx = dx - tx; dy = dy - ty; dz = dz - tz;
+      }
+      float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+      float r2 = xx + yy;
+      r2 = r2 + zz;
+      const bool in_r = valid && r2 < a.rc2;
+      const uint64_t mr = __builtin_amdgcn_ballot_w64(in_r);
+      const int pr = nr + below(mr);
+      // angular entries point into the radial list
+      const bool in_a = valid && r2 < a.rca2 && pr < a.max_rad;
+      const uint64_t ma = __builtin_amdgcn_ballot_w64(in_a);
+      const int pa = na + below(ma);
+      if (in_r && pr < a.max_rad) rad[(unsigned)pr] = j;
+      if (in_a && pa < a.max_ang) {
+        ang[(unsigned)pa] = j;
+        angpos[(unsigned)pa] = pr;
+      }
+      nr += __popcll(mr);
+      na += __popcll(ma);
+      if (nr > a.max_rad || na > a.max_ang) {
+        overflow = true;
+        nr = min(nr, a.max_rad);
+        na = min(na, a.max_ang);
+      }
+      j = jn;
+      pj = pn;
     }
   }
   if (lane == 0) {
