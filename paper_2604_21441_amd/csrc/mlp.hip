@@ -27,6 +27,7 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 constexpr float kLog2e = 1.4426950408889634f;
@@ -43,6 +44,12 @@ __device__ __forceinline__ v8bf to_bf16x8(const v4f& lo, const v4f& hi) {
   v8bf r;
   r[0] = (__bf16)lo[0]; r[1] = (__bf16)lo[1]; r[2] = (__bf16)lo[2]; r[3] = (__bf16)lo[3];
   r[4] = (__bf16)hi[0]; r[5] = (__bf16)hi[1]; r[6] = (__bf16)hi[2]; r[7] = (__bf16)hi[3];
+  return r;
+}
+
+__device__ __forceinline__ v4bf to_bf16x4(const v4f& v) {
+  v4bf r;
+  r[0] = (__bf16)v[0]; r[1] = (__bf16)v[1]; r[2] = (__bf16)v[2]; r[3] = (__bf16)v[3];
   return r;
 }
 
@@ -137,6 +144,19 @@ struct Own {  // number of row tiles r = w + 4 j owned by one wavefront
   static constexpr int n = (R + kWaves - 1) / kWaves;
 };
 
+// Layer outputs in LDS, per column tile c and row tile r (16 features):
+//   FP32: one v4f per lane at [(c * tiles + r) * 64 + lane];
+//   BF16: rounded once by the producer, two row tiles form the 16-byte B
+//     fragment of one 32-wide K block, [(c * tiles/2 + r/2) * 64 + lane],
+//     row tile r filling half r % 2 (the K permutation of the packed weights).
+template <bool BF16>
+__device__ __forceinline__ void put_tile(v4f* buf, int tiles, int c, int r, int lane, const v4f& v) {
+  if constexpr (BF16)
+    reinterpret_cast<v4bf*>(buf)[((c * (tiles / 2) + (r >> 1)) * 64 + lane) * 2 + (r & 1)] = to_bf16x4(v);
+  else
+    buf[(c * tiles + r) * 64 + lane] = v;
+}
+
 // out[j][c] = A-rows (w + 4 j) of W [R x K] times the K/16 LDS tiles `in[c][kb]`.
 template <int R, int K, bool BF16, int C>
 __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* in, int in_tiles, v4f (*out)[C],
@@ -168,7 +188,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
     for (int c = 0; c < C; ++c) {
       if (c >= cw) continue;   // a narrow tile (workgroup-uniform)
       if constexpr (BF16)
-        bv[c] = to_bf16x8(in[(c * in_tiles + 2 * kb) * 64 + lane], in[(c * in_tiles + 2 * kb + 1) * 64 + lane]);
+        bv[c] = reinterpret_cast<const v8bf*>(in)[(c * (in_tiles / 2) + kb) * 64 + lane];
       else
         bv[c] = in[(c * in_tiles + kb) * 64 + lane];
     }
@@ -192,8 +212,8 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   constexpr int TX = (K0 > N2 ? K0 : N2) / 16;        // tiles of buffer X (x, then H2, then delta2)
   constexpr int TA = (N1 > N3 ? N1 : N3) / 16;        // tiles of buffer A (H1, then delta3, then delta1)
   using Elem = typename std::conditional<BF16, __bf16, float>::type;
-  __shared__ v4f bufX[C * TX * 64];
-  __shared__ v4f bufA[C * TA * 64];
+  __shared__ v4f bufX[C * TX * (BF16 ? 32 : 64)];   // BF16 tiles take half the space
+  __shared__ v4f bufA[C * TA * (BF16 ? 32 : 64)];
   __shared__ float epart[kWaves][C * 16];
 
   const int w = threadIdx.x >> 6;
@@ -232,12 +252,26 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
 
     // stage x in fragment layout (again for every member: the buffer is reused
     // by later products): tile (c, kb), lane l holds x[row c*16 + l%16][16 kb + 4 (l/16) .. +3]
-    for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
-      const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
-      const int row = row0 + c * 16 + (l & 15);
-      v4f v = v4f{0.f, 0.f, 0.f, 0.f};
-      if (row < row_end) v = *reinterpret_cast<const v4f*>(a.x + (int64_t)row * a.stride + 16 * kb + 4 * (l >> 4));
-      bufX[(c * TX + kb) * 64 + l] = v;
+    if constexpr (BF16) {   // K block kb of 32 features: tiles 2 kb and 2 kb + 1
+      for (int t = threadIdx.x; t < C * (K0 / 32) * 64; t += 256) {
+        const int l = t & 63, kb = (t >> 6) % (K0 / 32), c = (t >> 6) / (K0 / 32);
+        const int row = row0 + c * 16 + (l & 15);
+        v4f lo = v4f{0.f, 0.f, 0.f, 0.f}, hi = lo;
+        if (row < row_end) {
+          const float* src = a.x + (int64_t)row * a.stride + 32 * kb + 4 * (l >> 4);
+          lo = *reinterpret_cast<const v4f*>(src);
+          hi = *reinterpret_cast<const v4f*>(src + 16);
+        }
+        reinterpret_cast<v8bf*>(bufX)[(c * (TX / 2) + kb) * 64 + l] = to_bf16x8(lo, hi);
+      }
+    } else {
+      for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
+        const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
+        const int row = row0 + c * 16 + (l & 15);
+        v4f v = v4f{0.f, 0.f, 0.f, 0.f};
+        if (row < row_end) v = *reinterpret_cast<const v4f*>(a.x + (int64_t)row * a.stride + 16 * kb + 4 * (l >> 4));
+        bufX[(c * TX + kb) * 64 + l] = v;
+      }
     }
     __syncthreads();
 
@@ -259,7 +293,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) h1[j][c][t] = celu_f(h1[j][c][t], alpha, inv_alpha_l2);
-          bufA[(c * TA + r) * 64 + lane] = h1[j][c];
+          put_tile<BF16>(bufA, TA, c, r, lane, h1[j][c]);
         }
       }
     }
@@ -284,7 +318,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) h2[j][c][t] = celu_f(h2[j][c][t], alpha, inv_alpha_l2);
-          bufX[(c * TX + r) * 64 + lane] = h2[j][c];
+          put_tile<BF16>(bufX, TX, c, r, lane, h2[j][c]);
         }
       }
     }
@@ -317,7 +351,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
             ep[c] += w4[t] * h;
             d[t] = w4[t] * celu_grad_from_h(h, inv_alpha);
           }
-          bufA[(c * TA + r) * 64 + lane] = d;
+          put_tile<BF16>(bufA, TA, c, r, lane, d);
         }
       }
     }
@@ -351,7 +385,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) d2[j][c][t] *= celu_grad_from_h(h2[j][c][t], inv_alpha);
-          bufX[(c * TX + r) * 64 + lane] = d2[j][c];
+          put_tile<BF16>(bufX, TX, c, r, lane, d2[j][c]);
         }
       }
     }
@@ -372,7 +406,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) d1[j][c][t] *= celu_grad_from_h(h1[j][c][t], inv_alpha);
-          bufA[(c * TA + r) * 64 + lane] = d1[j][c];
+          put_tile<BF16>(bufA, TA, c, r, lane, d1[j][c]);
         }
       }
     }

@@ -370,6 +370,24 @@ def test_mixed_network_tiling_bit_identical(P, w_water, w_hcno, boxes):
     assert np.array_equal(res[2][1], res[4][1])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
+    """All network kernels run the same matrix-core sequence per atom (same K
+    order, same operand rounding: BF16 activations are rounded once, by the
+    layer that produces them), so dE/dx and hence every force is bitwise the
+    same whichever kernel ran."""
+    pos, Z, box = boxes["c2"]
+    ref = None
+    for v in range(5):
+        m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision=prec)
+        m.set_variant("network", v)
+        F = _run(m, pos, Z, box)[1]
+        m.close()
+        if ref is None:
+            ref = F
+        assert np.array_equal(F, ref), f"network variant {v}"
+
+
 def test_neighbour_sets_batched_and_open(P, w_hcno):
     pos, Z, off = sy.walk_batch(6, seed=7)
     m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
