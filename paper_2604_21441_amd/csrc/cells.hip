@@ -60,8 +60,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
                                                   const int* __restrict__ idx,
                                                   const int* __restrict__ sigma,
                                                   const int* __restrict__ sys, Geometry g, LinkArgs L,
-                                                  int* __restrict__ key, int* __restrict__ bin_count,
-                                                  int* __restrict__ status) {
+                                                  int* __restrict__ key, int* __restrict__ rank,
+                                                  int* __restrict__ bin_count, int* __restrict__ status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const float3 p = nnp_position(pos, idx[t], L, g);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
   }
   int k = sigma[t] * g.n_bins + bin;
   key[t] = k;
-  atomicAdd(&bin_count[k], 1);
+  rank[t] = atomicAdd(&bin_count[k], 1);   // arrival order among the atoms of the key
 }
 
 // Exclusive scans of the bin histogram by one workgroup.
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
 // load and store is coalesced (per-thread runs of consecutive entries read
 // straight from memory are several times slower); each thread scans
 // kScanPer consecutive entries of the staged chunk.  The histogram itself is
-// left as it is: the scatter takes its cursors from it.
+// left as it is (the bin sort clears it).
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;
 constexpr int kScanChunk = kScanThreads * kScanPer;
@@ -242,15 +242,76 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ c
   if (threadIdx.x == 0) start[nb] = carry;
 }
 
-// Provisional slots: start of the key plus an atomically drawn place (the
-// histogram counts down to zero, which also clears it for the next call).
-__global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key, int n,
-                                                    const int* __restrict__ start, int* __restrict__ count,
-                                                    int* __restrict__ tmp) {
+// Provisional slots: start of the key plus the atom's arrival rank.
+__global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key, const int* __restrict__ rank, int n,
+                                                    const int* __restrict__ start, int* __restrict__ tmp) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const int k = key[t];
-  tmp[start[k] + atomicSub(&count[k], 1) - 1] = t;
+  tmp[start[key[t]] + rank[t]] = t;
+}
+
+// Scan and scatter in one launch, for histograms of at most one chunk: every
+// workgroup stages the histogram in LDS and scans it itself (a few KB to a
+// few tens of KB from L2, cheaper than a kernel boundary); workgroup 0 also
+// writes both scans for the later kernels.  Then each thread places one
+// atom at start[key] + rank.
+__global__ __launch_bounds__(kScanThreads) void k_scan_scatter(const int* __restrict__ count, int* __restrict__ start,
+                                                               int* __restrict__ cmstart, int S, int n_bins,
+                                                               const int* __restrict__ key,
+                                                               const int* __restrict__ rank, int n,
+                                                               int* __restrict__ tmp) {
+  __shared__ int wsum[2 * (kScanThreads / 64) + 1];
+  __shared__ int buf[kScanChunk + kScanChunk / kScanPer];
+  __shared__ int bufc[kScanChunk + kScanChunk / kScanPer];
+  const int nb = S * n_bins;   // <= kScanChunk (checked by the launcher)
+  const int t = blockIdx.x * kScanThreads + threadIdx.x;
+  const int k = t < n ? key[t] : 0;
+  const int rk = t < n ? rank[t] : 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int i = u * kScanThreads + threadIdx.x;
+    bufc[scan_pad(i)] = i < nb ? count[i] : 0;
+  }
+  __syncthreads();
+  int carry = 0;
+  if (blockIdx.x == 0) {   // bin-major starts (workgroup-uniform branch)
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int b = u * kScanThreads + threadIdx.x;
+      int tot = 0;
+#pragma unroll
+      for (int s = 0; s < kMaxSpecies; ++s)
+        if (s < S && b < n_bins) tot += bufc[scan_pad(s * n_bins + b)];
+      buf[scan_pad(b)] = tot;
+    }
+    __syncthreads();
+    scan_chunk(buf, wsum, &carry);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int b = u * kScanThreads + threadIdx.x;
+      if (b < n_bins) {
+        int r = buf[scan_pad(b)];
+#pragma unroll
+        for (int s = 0; s < kMaxSpecies; ++s)
+          if (s < S) {
+            cmstart[b * S + s] = r;
+            r += bufc[scan_pad(s * n_bins + b)];
+          }
+      }
+    }
+    __syncthreads();
+    carry = 0;
+  }
+  scan_chunk(bufc, wsum, &carry);   // species-major starts, in place
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      const int i = u * kScanThreads + threadIdx.x;
+      if (i < nb) start[i] = bufc[scan_pad(i)];
+    }
+    if (threadIdx.x == 0) start[nb] = carry;
+  }
+  if (t < n) tmp[bufc[scan_pad(k)] + rk] = t;
 }
 
 // One wavefront per bin: the atomically scattered entries of the bin are
@@ -267,10 +328,12 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
                                                     float4* __restrict__ spos,
                                                     int* __restrict__ slot_atom,
                                                     int* __restrict__ order, int* __restrict__ sbin,
-                                                    int* __restrict__ islot, int* __restrict__ pcount) {
+                                                    int* __restrict__ islot, int* __restrict__ pcount,
+                                                    int* __restrict__ count) {
   int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= n_bins_total) return;
+  if (lane == 0) count[wave] = 0;   // the histogram starts from zero in the next call
   int b0 = start[wave], b1 = start[wave + 1];
   const int sp = wave / g.n_bins, bin = wave - sp * g.n_bins;
   const int o0 = cmstart[bin * S + sp];
@@ -865,21 +928,27 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   int nb = m.S * g.n_bins;
   if (n > 0) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
-                       m.d_sigma, m.d_sys, g, L, m.d_key, m.d_bin_count, m.d_status);
+                       m.d_sigma, m.d_sys, g, L, m.d_key, m.d_rank, m.d_bin_count, m.d_status);
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
-                     m.S, g.n_bins);
+  const bool fused = n > 0 && g.periodic && nb <= kScanChunk;
+  if (fused) {
+    hipLaunchKernelGGL(k_scan_scatter, dim3(blocks_for(n, kScanThreads)), dim3(kScanThreads), 0, st, m.d_bin_count,
+                       m.d_bin_start, m.d_cmstart, m.S, g.n_bins, m.d_key, m.d_rank, n, m.d_tmp);
+  } else {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
+                       m.S, g.n_bins);
+  }
   if (n > 0 && !g.periodic) {
     hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
                        m.d_sigma, m.d_idx, pos, g, L, m.d_cmstart, m.d_perm, m.d_spos, m.d_slot_atom,
                        m.d_order, m.d_bin_count, m.d_sbin, m.d_islot, m.d_pcount);
   } else if (n > 0) {
-    int* tmp = m.d_tmp;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, n,
-                       m.d_bin_start, m.d_bin_count, tmp);
+    if (!fused)
+      hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, m.d_rank, n,
+                         m.d_bin_start, m.d_tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
-                       m.d_bin_start, nb, tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
-                       m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin, m.d_islot, m.d_pcount);
+                       m.d_bin_start, nb, m.d_tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
+                       m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin, m.d_islot, m.d_pcount, m.d_bin_count);
   }
   return hipGetLastError();
 }

@@ -164,6 +164,7 @@ struct nnp_model {
   int* d_order = nullptr;      // [max_atoms] slots in bin-major visiting order
   int* d_perm = nullptr;       // slot -> NNP-local atom
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
+  int* d_rank = nullptr;       // arrival rank of each atom among the atoms of its bin key
   float4* d_spos = nullptr;    // slot -> position (w = species bits)
   int* d_slot_atom = nullptr;  // slot -> atom index
   int* d_sbin = nullptr;       // slot -> cell coordinates x<<20 | y<<10 | z (periodic) or system
