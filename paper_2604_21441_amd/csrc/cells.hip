@@ -340,10 +340,18 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
   // the cell's coordinates, packed for the neighbour search
   const int cz = bin % g.nc[2], cxy = bin / g.nc[2];
   const int packed = ((cxy / g.nc[1]) << 20) | ((cxy % g.nc[1]) << 10) | cz;
+  const int cnt = b1 - b0;
+  // bins of up to 64 atoms: one entry per lane, ranked against the others
+  // with lane reads (no memory round trip per comparison)
+  const int mine = lane < cnt ? tmp[b0 + lane] : 0;
   for (int e = b0 + lane; e < b1; e += 64) {
     int t = tmp[e];
     int rank = 0;
-    for (int q = b0; q < b1; ++q) rank += tmp[q] < t;
+    if (cnt <= 64) {
+      for (int q = 0; q < cnt; ++q) rank += __builtin_amdgcn_readlane(mine, q) < t;
+    } else {
+      for (int q = b0; q < b1; ++q) rank += tmp[q] < t;
+    }
     int slot = b0 + rank;
     perm[slot] = t;
     order[o0 + rank] = slot;
