@@ -386,7 +386,7 @@ def roofline(res, cfg, prec, stage, workload, periodic):
     if stage in ("adjoint", "descriptor"):
         if stage == "adjoint":
             ops = OPS_BWD_RAD_PAIR * res["rad_pairs"] + OPS_BWD_TRIPLET * res["triplets"]
-            byts = n * (4 * D + 16) + 16 * res["rad_pairs"] + 24 * n
+            byts = n * (4 * D + 16) + 12 * res["rad_pairs"] + 24 * n
         else:
             ops = OPS_FWD_RAD_PAIR * res["rad_pairs"] + OPS_FWD_TRIPLET * res["triplets"]
             byts = n * (16 + 4 * D)
@@ -396,7 +396,7 @@ def roofline(res, cfg, prec, stage, workload, periodic):
                 "traffic": traffic, "algorithmic_per_launch": ops, "hbm_GBs": byts / t / 1e9}
     # memory-bound stages
     byts = {"neighbours": n * 16 + 4 * res["rad_pairs"] + 8 * res["rad_pairs"],
-            "gather": 16 * res["rad_pairs"] + 24 * n + 48 * n,
+            "gather": 12 * res["rad_pairs"] + 24 * n + 48 * n,
             "cells": 16 * n + 16 * n,
             "energy": 8 * (n // 16)}.get(stage, 16 * n)
     ach = byts / t / 1e9

@@ -481,7 +481,7 @@ struct BwdArgs {
   const int* ang_off;
   int max_rad, max_ang, n;
   const float* g;
-  float4* contrib;   // [n][max_rad]
+  float3* contrib;   // [n][max_rad]
   double* self;      // [n][3]
 };
 
@@ -687,7 +687,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
       if (jrow[mid] < i) lo = mid + 1; else hi = mid;
     }
     if (lo <= hi && jrow[lo] == i)
-      a.contrib[(int64_t)j * a.max_rad + lo] = make_float4((float)-sx[t], (float)-sy[t], (float)-sz[t], 0.f);
+      a.contrib[(int64_t)j * a.max_rad + lo] = make_float3((float)-sx[t], (float)-sy[t], (float)-sz[t]);
   }
   // 6. the centre's own total
   double dx = part_sum_d<LANES>((double)fx), dy = part_sum_d<LANES>((double)fy), dz = part_sum_d<LANES>((double)fz);
@@ -750,7 +750,7 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int sys) {
 // With `assign` the sum overwrites F_atom (every row of the output is an NNP
 // atom and the call does not accumulate), which saves clearing it first.
 // Blocks from gather_blocks on reduce the energies instead.
-__global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restrict__ contrib,
+__global__ __launch_bounds__(kBlock) void k_force_gather(const float3* __restrict__ contrib,
                                                          const double* __restrict__ self,
                                                          const int* __restrict__ rad_off,
                                                          const int* __restrict__ slot_atom, int n, int S,
@@ -767,9 +767,9 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const float4* __restric
   double fx = 0.0, fy = 0.0, fz = 0.0;
   if (i < n) {
     const int nr = rad_off[(int64_t)i * (S + 1) + S];
-    const float4* row = contrib + (int64_t)i * max_rad;
+    const float3* row = contrib + (int64_t)i * max_rad;   // 16 lanes read 192 contiguous bytes
     for (int t = sub; t < nr; t += 16) {
-      float4 v = row[t];
+      const float3 v = row[t];
       fx += v.x; fy += v.y; fz += v.z;
     }
   }

@@ -176,7 +176,7 @@ struct nnp_model {
   int* d_rad_off = nullptr;
   int* d_ang_off = nullptr;
   int* d_angpos = nullptr;     // [n][max_ang] position of each angular neighbour in the radial list
-  float4* d_contrib = nullptr; // [n][max_rad] force on atom i from the centre at its radial slot
+  float3* d_contrib = nullptr; // [n][max_rad] force on atom i from the centre at its radial slot
   double* d_self = nullptr;    // [n][3] force on each atom from its own environment
   double* d_part = nullptr;    // per-wavefront FP64 energy partials
   int max_part = 0;
