@@ -41,6 +41,9 @@ WORKLOADS = {
     "c5a": dict(kind="water", n_mol=87000, L=137.7,
                 desc="periodic water box, 87,000 molecules (261,000 atoms), L=137.7 A"),
     "c4": dict(kind="batch", n_sys=256, desc="256 open H/C/N/O walk molecules of 24-300 atoms, one batched call"),
+    "c5b": dict(kind="solute_mm",
+                desc="60-atom H/C/N/O walk solute in 10,000 fixed-charge MM waters (30,000 point charges "
+                     "entering as the extra input channel, 12 A), periodic L=68.3 A"),
 }
 
 # Peaks (MI355X, published): HBM 8 TB/s; dense MFMA FP32 157.3 TFLOP/s, BF16 2.5 PFLOP/s.
@@ -50,16 +53,23 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic VALU lane-operations per unit of work (transcendental = 4), derived in the design doc.
+# Algorithmic VALU lane-operations per unit of work (transcendental = 4): the arithmetic the
+# method needs per radial pair and per angular triplet, forward and adjoint.
 OPS_FWD_RAD_PAIR = 155
 OPS_FWD_TRIPLET = 150
 OPS_BWD_RAD_PAIR = 200
 OPS_BWD_TRIPLET = 300
+# MM potential channel, per (NNP atom, MM charge) pair tested: minimum-image
+# displacement and r^2 (16), inside the cutoff rsq, cos and the charge term (13),
+# the wavefront sum over MM lanes (12); the adjoint adds sin, d(fc/r)/dr, the
+# pair vector and three wavefront sums (80 in all).  Transcendentals count 4.
+OPS_MM_FWD_PAIR = 40
+OPS_MM_BWD_PAIR = 80
 
 
 # rocprofv3 summaries committed under profiles/ (written by --summarize-profiles).
 PROFILE_TAGS = {"c1": "water192", "c2": "water12288", "c3": "water98304", "c5a": "water261000",
-                "c4": "hcno_batch256"}
+                "c4": "hcno_batch256", "c5b": "hcno60_mm30000"}
 CSRC = os.path.join(ROOT, "paper_2604_21441_amd", "csrc")
 CALIB_BYTES = 1 << 30   # --calib-copy: one device copy of this many bytes (read + write)
 
@@ -105,7 +115,8 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
         return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {cols}>"
     if stage == "adjoint":
         return ["k_desc_bwd<64>", "k_desc_bwd<32>"][v.get("adjoint", 0)]
-    return {"gather": "k_force_gather", "energy": "k_force_gather"}.get(stage)
+    return {"gather": "k_force_gather", "energy": "k_force_gather", "mm": "k_mm_fwd",
+            "mm_adjoint": "k_mm_bwd"}.get(stage)
 
 
 def profile_traffic(workload, kernel):
@@ -234,10 +245,14 @@ def build_inputs(name):
     if w["kind"] == "water":
         cfg = sy.model_config("water")
         pos, Z, box = sy.water_box(w["n_mol"], w["L"], seed=0)
-        return cfg, dict(pos=pos, Z=Z, box=box, offsets=None)
+        return cfg, dict(pos=pos, Z=Z, box=box, offsets=None, mm_pos=None, mm_q=None)
+    if w["kind"] == "solute_mm":
+        cfg = sy.model_config("hcno_mm")
+        s = sy.solute_in_water(seed=0)
+        return cfg, dict(pos=s["pos"], Z=s["Z"], box=s["box"], offsets=None, mm_pos=s["mm_pos"], mm_q=s["mm_q"])
     cfg = sy.model_config("hcno")
     pos, Z, off = sy.walk_batch(w["n_sys"], seed=0)
-    return cfg, dict(pos=pos, Z=Z, box=None, offsets=np.asarray(off, np.int32))
+    return cfg, dict(pos=pos, Z=Z, box=None, offsets=np.asarray(off, np.int32), mm_pos=None, mm_q=None)
 
 
 def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
@@ -256,6 +271,15 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
         F = torch.empty((n, 3), dtype=torch.float64, device="cuda")
         first = lambda: m.compute_batch(d, inp["Z"], inp["offsets"], out=(E, F))
         call = lambda: m.compute_batch(d, None, inp["offsets"], out=(E, F))
+    elif inp["mm_pos"] is not None:   # MM charges through the extra input channel
+        dm = torch.from_numpy(inp["mm_pos"]).cuda()
+        dq = torch.from_numpy(inp["mm_q"]).cuda()
+        m.reserve(n, 1, dm.shape[0])
+        E = torch.empty(1, dtype=torch.float64, device="cuda")
+        F = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        Fmm = torch.empty((dm.shape[0], 3), dtype=torch.float64, device="cuda")
+        first = lambda: m.compute(d, inp["Z"], inp["box"], mm_pos=dm, mm_q=dq, out=(E, F, Fmm))
+        call = lambda: m.compute(d, None, inp["box"], mm_pos=dm, mm_q=dq, out=(E, F, Fmm))
     else:
         m.reserve(n)
         E = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -269,6 +293,8 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
         raise RuntimeError(f"device status {st} after the first call")
     E_first = E.detach().cpu().numpy().astype(float)
     F_first = F.detach().cpu().numpy()
+    if inp.get("mm_pos") is not None:   # forces on NNP atoms, then on MM atoms
+        F_first = np.concatenate([F_first, Fmm.detach().cpu().numpy()])
     if autotune:
         m.autotune(10)
     tuned = m.variants()
@@ -309,6 +335,7 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
         "rad_pairs": int(cnt[:, 0].sum()),
         "triplets": int((cnt[:, 1].astype(np.int64) * (cnt[:, 1] - 1) // 2).sum()),
         "n": n,
+        "n_mm": 0 if inp.get("mm_pos") is None else len(inp["mm_q"]),
         "tuned": tuned,
     }
     m.close()
@@ -322,6 +349,10 @@ def oracle_reference(cfg, w, inp, sample_centres):
     if inp["offsets"] is not None:
         E, F = orc.evaluate_batch(inp["pos"], inp["Z"], inp["offsets"], cfg, w)
         return {"E": E, "F": F, "atoms": np.arange(len(inp["Z"]))}
+    if inp.get("mm_pos") is not None:
+        r = orc.evaluate(inp["pos"], inp["Z"], cfg, w, box=inp["box"], mm_pos=inp["mm_pos"], mm_q=inp["mm_q"])
+        F = np.concatenate([r["F"], r["F_mm"]])
+        return {"E": np.array([r["E"]]), "F": F, "atoms": np.arange(len(F))}
     if sample_centres is None:
         r = orc.evaluate(inp["pos"], inp["Z"], cfg, w, box=inp["box"])
         return {"E": np.array([r["E"]]), "F": r["F"], "atoms": np.arange(len(inp["Z"]))}
@@ -344,6 +375,11 @@ def cpu_baseline(cfg, w, inp, reps):
         sample = f"first {k} molecules ({int(off[k])} atoms) of the batch, E+F, median of {reps}"
         atoms = int(off[k])
         fn = lambda: orc.evaluate_batch(inp["pos"][sub], inp["Z"][sub], off[:k + 1], cfg, w)
+    elif inp.get("mm_pos") is not None:
+        sample = f"full {n}-atom solute with its {len(inp['mm_q'])} MM charges, E+F, median of {reps}"
+        atoms = n
+        fn = lambda: orc.evaluate(inp["pos"], inp["Z"], cfg, w, box=inp["box"], mm_pos=inp["mm_pos"],
+                                  mm_q=inp["mm_q"])
     elif n <= 20000:
         sample = f"full {n}-atom system, E+F, median of {reps}"
         atoms = n
@@ -394,6 +430,11 @@ def roofline(res, cfg, prec, stage, workload, periodic):
         return {"kernel": kernel, "bound": "alu",
                 "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
                 "traffic": traffic, "algorithmic_per_launch": ops, "hbm_GBs": byts / t / 1e9}
+    if stage in ("mm", "mm_adjoint"):   # all (NNP atom, MM charge) pairs are tested
+        ops = (OPS_MM_FWD_PAIR if stage == "mm" else OPS_MM_BWD_PAIR) * n * res["n_mm"]
+        ach = ops / t / 1e12
+        return {"kernel": kernel, "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                "frac": ach / PEAK_VALU_TOPS, "traffic": traffic, "algorithmic_per_launch": ops}
     # memory-bound stages
     byts = {"neighbours": n * 16 + 4 * res["rad_pairs"] + 8 * res["rad_pairs"],
             "gather": 12 * res["rad_pairs"] + 24 * n + 48 * n,
@@ -484,7 +525,8 @@ def main(argv=None):
             if ref["E"] is not None:
                 sizes = np.diff(inp["offsets"]) if inp["offsets"] is not None else np.array([n])
                 entry["energy_err_per_atom_eV"] = float(np.max(np.abs(r["E"] - ref["E"]) / sizes))
-            entry["rmse_over"] = "all atoms" if a.size == n else f"{a.size} sampled atoms"
+            entry["rmse_over"] = ("all NNP and MM atoms" if inp.get("mm_pos") is not None else
+                                  "all atoms" if a.size == n else f"{a.size} sampled atoms")
         report_forms[prec] = entry
     r32, r16 = forms["fp32"], forms["bf16"]
     report_forms["bf16"]["force_rel_rmse_vs_fp32"] = float(np.linalg.norm(r16["F"] - r32["F"]) /

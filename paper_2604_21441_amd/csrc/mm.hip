@@ -3,15 +3,19 @@
 // interface passes MM positions and charges, and the model may put forces on
 // MM atoms):
 //   phi_i = ke * sum_j q_j fc(r_ij; Rm) / r_ij     over MM atoms j, r_ij < Rm
-// The pass is all-pairs over (NNP atom, MM atom): one lane per MM atom, the
-// wavefront walks the NNP atoms together and reduces each atom's sum across
-// lanes.  Intended for ML regions of up to a few thousand atoms.
+// The pass is all-pairs over (NNP atom, MM atom): one lane per MM atom; the
+// grid's second dimension splits the NNP atoms into chunks of kNnpChunk, so
+// that a small ML region still gives many wavefronts, and each wavefront
+// walks its chunk (unrolled, so that the reductions of several atoms are in
+// flight together) and reduces each atom's sum across lanes.  Intended for ML
+// regions of up to a few thousand atoms.
 #include "nnp_internal.h"
 
 namespace nnp {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kNnpChunk = 16;   // NNP atoms per wavefront
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -49,7 +53,9 @@ __global__ __launch_bounds__(kBlock) void k_mm_fwd(const float4* __restrict__ sp
   }
   const float rm2 = p.mm_cutoff * p.mm_cutoff;
   const float inv2rm = 0.5f / p.mm_cutoff;
-  for (int i = 0; i < n; ++i) {
+  const int i0 = blockIdx.y * kNnpChunk, i1 = min(n, i0 + kNnpChunk);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
     float4 pi = spos[i];
     float dx, dy, dz, r2;
     mm_disp(pi, yx, yy, yz, g, dx, dy, dz, r2);
@@ -95,7 +101,9 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
   const float inv2rm = 0.5f / p.mm_cutoff;
   const float dfc_s = -0.5f * 3.14159265358979323846f / p.mm_cutoff;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int i = 0; i < n; ++i) {
+  const int i0 = blockIdx.y * kNnpChunk, i1 = min(n, i0 + kNnpChunk);
+#pragma unroll 4
+  for (int i = i0; i < i1; ++i) {
     float4 pi = spos[i];
     float gi = gx[(int64_t)i * p.stride + p.D];
     float dx, dy, dz, r2;
@@ -121,9 +129,15 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
       unsafeAtomicAdd(f + 2, (double)sz);
     }
   }
-  if (ok && mm_forces != nullptr) {
+  if (ok && mm_forces != nullptr) {   // one NNP chunk: this lane owns the row; else several chunks add
     double* f = mm_forces + 3 * (int64_t)j;
-    f[0] += fx; f[1] += fy; f[2] += fz;
+    if (gridDim.y == 1) {
+      f[0] += fx; f[1] += fy; f[2] += fz;
+    } else if (fx != 0.0 || fy != 0.0 || fz != 0.0) {
+      unsafeAtomicAdd(f + 0, fx);
+      unsafeAtomicAdd(f + 1, fy);
+      unsafeAtomicAdd(f + 2, fz);
+    }
   }
 }
 
@@ -134,8 +148,8 @@ hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, con
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_f64, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_phi, n);
   if (n_mm > 0) {
-    hipLaunchKernelGGL(k_mm_fwd, dim3((n_mm + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_spos, n,
-                       mm_pos, mm_q, n_mm, m.dp, m.geo, m.d_phi);
+    hipLaunchKernelGGL(k_mm_fwd, dim3((n_mm + kBlock - 1) / kBlock, (n + kNnpChunk - 1) / kNnpChunk), dim3(kBlock),
+                       0, st, m.d_spos, n, mm_pos, mm_q, n_mm, m.dp, m.geo, m.d_phi);
   }
   hipLaunchKernelGGL(k_mm_finish, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_phi, n, m.dp,
                      m.d_x);
@@ -145,8 +159,9 @@ hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, con
 hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
                          double* forces, double* mm_forces, hipStream_t st) {
   if (n == 0 || n_mm == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mm_bwd, dim3((n_mm + kBlock - 1) / kBlock), dim3(kBlock), 0, st, m.d_spos,
-                     m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.dp, m.geo, forces, mm_forces, m.d_link_F);
+  hipLaunchKernelGGL(k_mm_bwd, dim3((n_mm + kBlock - 1) / kBlock, (n + kNnpChunk - 1) / kNnpChunk), dim3(kBlock),
+                     0, st, m.d_spos, m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.dp, m.geo, forces, mm_forces,
+                     m.d_link_F);
   return hipGetLastError();
 }
 
