@@ -112,6 +112,8 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
         cols = {1: 1, 2: 2, 3: 4 if k0 <= 128 else 2}.get(nv)
         if nv == 4:
             return f"k_mlp_mixed<{dims}>"
+        if nv in (5, 6, 7):
+            return f"k_mlp_split8<{dims}, {1 if nv == 5 else 2}, {'true' if nv == 6 else 'false'}>"
         return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {cols}>"
     if stage == "adjoint":
         return ["k_desc_bwd<64>", "k_desc_bwd<32>"][v.get("adjoint", 0)]

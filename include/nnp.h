@@ -253,7 +253,8 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
 /*
  * Autotuner.  Several stages have more than one kernel variant (network:
  * register-resident wavefronts or row-split workgroups of 16, 32 or 64 atoms,
- * or of 32 atoms with 16 for the smallest species;
+ * or of 32 atoms with 16 for the smallest species, with four or eight
+ * wavefronts;
  * descriptor forward: a wavefront, a 16-lane or an 8-lane row per atom; descriptor
  * adjoint: a wavefront or half a wavefront per atom; neighbour search: one
  * wavefront per atom, or several per cell sharing its centre atoms).
@@ -290,7 +291,9 @@ typedef enum {
  *   network: 0 register-resident wavefronts; 1 / 2 / 3 row-split workgroups
  *     of 16 / 32 / 64 atoms (64 for water-sized networks only, wider ones
  *     use 32); 4 workgroups of 32 atoms, 16 for the species with the fewest
- *     atoms (more even workgroups for small systems);
+ *     atoms (more even workgroups for small systems); 5 / 6 / 7 as 1 / 4 / 2
+ *     with eight wavefronts per workgroup instead of four (shorter chains
+ *     per tile, for systems with few tiles or wide networks);
  *   descriptor adjoint: 0 one wavefront per atom; 1 half a wavefront per atom.
  * All variants compute the same quantities (integer stages bit-identically,
  * floating point to rounding).

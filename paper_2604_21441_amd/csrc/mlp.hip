@@ -137,11 +137,9 @@ __device__ __forceinline__ float celu_grad_from_h(float h, float inv_alpha) {
 // serves C matrix-core steps) and publishes them in LDS, in the same fragment
 // layout, for the next product.  Each wavefront keeps its own post-activation
 // tiles in registers for the CELU derivative of the backward pass.
-constexpr int kWaves = 4;
-
-template <int R>
-struct Own {  // number of row tiles r = w + 4 j owned by one wavefront
-  static constexpr int n = (R + kWaves - 1) / kWaves;
+template <int R, int NW>
+struct Own {  // number of row tiles r = w + NW j owned by one of NW wavefronts
+  static constexpr int n = (R + NW - 1) / NW;
 };
 
 // Layer outputs in LDS, per column tile c and row tile r (16 features):
@@ -158,10 +156,10 @@ __device__ __forceinline__ void put_tile(v4f* buf, int tiles, int c, int r, int 
 }
 
 // out[j][c] = A-rows (w + 4 j) of W [R x K] times the K/16 LDS tiles `in[c][kb]`.
-template <int R, int K, bool BF16, int C>
+template <int R, int K, bool BF16, int C, int NW>
 __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* in, int in_tiles, v4f (*out)[C],
                                          int w, int lane, int cw) {
-  constexpr int NJ = Own<R>::n;
+  constexpr int NJ = Own<R, NW>::n;
   constexpr int KB = BF16 ? K / 32 : K / 16;
   constexpr int kPrefetch = PrefetchDepth<BF16, (16 * R > 160 || K > 160)>::value;
   using F = typename Frag<BF16>::T;
@@ -171,7 +169,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
   for (int p = 0; p < kPrefetch; ++p)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int r = w + kWaves * j;
+      const int r = w + NW * j;
       if (p < KB && r < R) ring[p][j] = Wp[(r * KB + p) * 64 + lane];
     }
 #pragma unroll
@@ -179,7 +177,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
     F cur[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int r = w + kWaves * j;
+      const int r = w + NW * j;
       cur[j] = ring[kb % kPrefetch][j];
       if (kb + kPrefetch < KB && r < R) ring[kb % kPrefetch][j] = Wp[(r * KB + kb + kPrefetch) * 64 + lane];
     }
@@ -194,7 +192,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int r = w + kWaves * j;
+      const int r = w + NW * j;
       if (r < R) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -204,7 +202,7 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
   }
 }
 
-template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED>
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED, int NW>
 __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
   constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
@@ -214,7 +212,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   using Elem = typename std::conditional<BF16, __bf16, float>::type;
   __shared__ v4f bufX[C * TX * (BF16 ? 32 : 64)];   // BF16 tiles take half the space
   __shared__ v4f bufA[C * TA * (BF16 ? 32 : 64)];
-  __shared__ float epart[kWaves][C * 16];
+  __shared__ float epart[NW][C * 16];
 
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -253,7 +251,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     // stage x in fragment layout (again for every member: the buffer is reused
     // by later products): tile (c, kb), lane l holds x[row c*16 + l%16][16 kb + 4 (l/16) .. +3]
     if constexpr (BF16) {   // K block kb of 32 features: tiles 2 kb and 2 kb + 1
-      for (int t = threadIdx.x; t < C * (K0 / 32) * 64; t += 256) {
+      for (int t = threadIdx.x; t < C * (K0 / 32) * 64; t += 64 * NW) {
         const int l = t & 63, kb = (t >> 6) % (K0 / 32), c = (t >> 6) / (K0 / 32);
         const int row = row0 + c * 16 + (l & 15);
         v4f lo = v4f{0.f, 0.f, 0.f, 0.f}, hi = lo;
@@ -265,7 +263,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         reinterpret_cast<v8bf*>(bufX)[(c * (TX / 2) + kb) * 64 + l] = to_bf16x8(lo, hi);
       }
     } else {
-      for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 256) {
+      for (int t = threadIdx.x; t < C * (K0 / 16) * 64; t += 64 * NW) {
         const int l = t & 63, kb = (t >> 6) % (K0 / 16), c = (t >> 6) / (K0 / 16);
         const int row = row0 + c * 16 + (l & 15);
         v4f v = v4f{0.f, 0.f, 0.f, 0.f};
@@ -276,18 +274,18 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     __syncthreads();
 
     // ---- layer 1: h1 = celu(W1 x + b1)       X -> A
-    v4f h1[Own<N1>::n][C];
+    v4f h1[Own<N1, NW>::n][C];
 #pragma unroll
-    for (int j = 0; j < Own<N1>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N1, NW>::n; ++j) {
+      const int r = w + NW * j;
       const v4f bias = r < N1 / 16 ? *reinterpret_cast<const v4f*>(V + ob1 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < C; ++c) h1[j][c] = bias;
     }
-    gemm_lds<N1 / 16, K0, BF16, C>(Wm + oF1, bufX, TX, h1, w, lane, cw);
+    gemm_lds<N1 / 16, K0, BF16, C, NW>(Wm + oF1, bufX, TX, h1, w, lane, cw);
 #pragma unroll
-    for (int j = 0; j < Own<N1>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N1, NW>::n; ++j) {
+      const int r = w + NW * j;
       if (r < N1 / 16) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -300,19 +298,19 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     __syncthreads();
 
     // ---- layer 2: h2 = celu(W2 h1 + b2)      A -> X
-    v4f h2[Own<N2>::n][C];
+    v4f h2[Own<N2, NW>::n][C];
 #pragma unroll
-    for (int j = 0; j < Own<N2>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N2, NW>::n; ++j) {
+      const int r = w + NW * j;
       const v4f bias = r < N2 / 16 ? *reinterpret_cast<const v4f*>(V + ob2 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < C; ++c) h2[j][c] = bias;
     }
-    gemm_lds<N2 / 16, N1, BF16, C>(Wm + oF2, bufA, TA, h2, w, lane, cw);
+    gemm_lds<N2 / 16, N1, BF16, C, NW>(Wm + oF2, bufA, TA, h2, w, lane, cw);
     __syncthreads();   // everyone has read A (h1) and X (x) before X is overwritten
 #pragma unroll
-    for (int j = 0; j < Own<N2>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N2, NW>::n; ++j) {
+      const int r = w + NW * j;
       if (r < N2 / 16) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -325,21 +323,21 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     __syncthreads();
 
     // ---- layer 3 and the output layer; delta3 = w4 o celu'(h3)   X -> A
-    v4f h3[Own<N3>::n][C];
+    v4f h3[Own<N3, NW>::n][C];
 #pragma unroll
-    for (int j = 0; j < Own<N3>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N3, NW>::n; ++j) {
+      const int r = w + NW * j;
       const v4f bias = r < N3 / 16 ? *reinterpret_cast<const v4f*>(V + ob3 + 16 * r + 4 * q) : v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < C; ++c) h3[j][c] = bias;
     }
-    gemm_lds<N3 / 16, N2, BF16, C>(Wm + oF3, bufX, TX, h3, w, lane, cw);
+    gemm_lds<N3 / 16, N2, BF16, C, NW>(Wm + oF3, bufX, TX, h3, w, lane, cw);
     float ep[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) ep[c] = 0.f;
 #pragma unroll
-    for (int j = 0; j < Own<N3>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N3, NW>::n; ++j) {
+      const int r = w + NW * j;
       if (r < N3 / 16) {
         const v4f w4 = *reinterpret_cast<const v4f*>(V + ow4 + 16 * r + 4 * q);
 #pragma unroll
@@ -366,20 +364,24 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     if (w == 0) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        e_acc[c] += epart[0][c * 16 + col] + epart[1][c * 16 + col] + epart[2][c * 16 + col] +
-                    epart[3][c * 16 + col] + V[ob4];
+      {
+        float e = 0.f;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) e += epart[u][c * 16 + col];
+        e_acc[c] += e + V[ob4];
+      }
     }
 
     // ---- delta2 = (W3^T delta3) o celu'(h2)    A -> X
-    v4f d2[Own<N2>::n][C];
+    v4f d2[Own<N2, NW>::n][C];
 #pragma unroll
-    for (int j = 0; j < Own<N2>::n; ++j)
+    for (int j = 0; j < Own<N2, NW>::n; ++j)
 #pragma unroll
       for (int c = 0; c < C; ++c) d2[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    gemm_lds<N2 / 16, N3, BF16, C>(Wm + oB3, bufA, TA, d2, w, lane, cw);
+    gemm_lds<N2 / 16, N3, BF16, C, NW>(Wm + oB3, bufA, TA, d2, w, lane, cw);
 #pragma unroll
-    for (int j = 0; j < Own<N2>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N2, NW>::n; ++j) {
+      const int r = w + NW * j;
       if (r < N2 / 16) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -392,15 +394,15 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     __syncthreads();
 
     // ---- delta1 = (W2^T delta2) o celu'(h1)    X -> A
-    v4f d1[Own<N1>::n][C];
+    v4f d1[Own<N1, NW>::n][C];
 #pragma unroll
-    for (int j = 0; j < Own<N1>::n; ++j)
+    for (int j = 0; j < Own<N1, NW>::n; ++j)
 #pragma unroll
       for (int c = 0; c < C; ++c) d1[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-    gemm_lds<N1 / 16, N2, BF16, C>(Wm + oB2, bufX, TX, d1, w, lane, cw);
+    gemm_lds<N1 / 16, N2, BF16, C, NW>(Wm + oB2, bufX, TX, d1, w, lane, cw);
 #pragma unroll
-    for (int j = 0; j < Own<N1>::n; ++j) {
-      const int r = w + kWaves * j;
+    for (int j = 0; j < Own<N1, NW>::n; ++j) {
+      const int r = w + NW * j;
       if (r < N1 / 16) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -414,15 +416,15 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
 
     // ---- dE/dx = W1^T delta1 (row tiles over the input features), to memory
     {
-      v4f gx[Own<K0 / 16>::n][C];
+      v4f gx[Own<K0 / 16, NW>::n][C];
 #pragma unroll
-      for (int j = 0; j < Own<K0 / 16>::n; ++j)
+      for (int j = 0; j < Own<K0 / 16, NW>::n; ++j)
 #pragma unroll
         for (int c = 0; c < C; ++c) gx[j][c] = v4f{0.f, 0.f, 0.f, 0.f};
-      gemm_lds<K0 / 16, N1, BF16, C>(Wm + oB1, bufA, TA, gx, w, lane, cw);
+      gemm_lds<K0 / 16, N1, BF16, C, NW>(Wm + oB1, bufA, TA, gx, w, lane, cw);
 #pragma unroll
-      for (int j = 0; j < Own<K0 / 16>::n; ++j) {
-        const int r = w + kWaves * j;
+      for (int j = 0; j < Own<K0 / 16, NW>::n; ++j) {
+        const int r = w + NW * j;
         if (r < K0 / 16) {
 #pragma unroll
           for (int c = 0; c < C; ++c) {
@@ -464,7 +466,15 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
 
 template <int K0, int N1, int N2, int N3, bool BF16, int C>
 __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a, float alpha) {
-  mlp_split_body<K0, N1, N2, N3, BF16, C, false>(a, alpha);
+  mlp_split_body<K0, N1, N2, N3, BF16, C, false, 4>(a, alpha);
+}
+
+// Eight wavefronts per 16-atom tile: each owns half as many row tiles of
+// every product, so a tile's chain is shorter.  For systems with too few
+// tiles to fill the GPU (a small ML region: a tile per species).
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED>
+__global__ __launch_bounds__(512) void k_mlp_split8(MlpArgs a, float alpha) {
+  mlp_split_body<K0, N1, N2, N3, BF16, C, MIXED, 8>(a, alpha);
 }
 
 // Mixed tiling: tiles of 32 atoms, of 16 for the species with the fewest
@@ -474,7 +484,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
 // in the uniform tiling.
 template <int K0, int N1, int N2, int N3, bool BF16>
 __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_mixed(MlpArgs a, float alpha) {
-  mlp_split_body<K0, N1, N2, N3, BF16, 2, true>(a, alpha);
+  mlp_split_body<K0, N1, N2, N3, BF16, 2, true, 4>(a, alpha);
 }
 
 // Register-resident variant: each wavefront owns 16 atoms and keeps the whole
@@ -663,6 +673,18 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
     const int64_t waves = (n + 15) / 16 + m.S;
     hipLaunchKernelGGL((k_mlp_reg<K0, N1, N2, N3, BF16>), dim3((unsigned)((waves * 64 + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, a, m.celu_alpha);
+  } else if (variant == 5) {   // 16 atoms per workgroup of eight wavefronts
+    const int64_t tiles = (n + 15) / 16 + m.S;
+    hipLaunchKernelGGL((k_mlp_split8<K0, N1, N2, N3, BF16, 1, false>), dim3((unsigned)tiles), dim3(512), 0, st, a,
+                       m.celu_alpha);
+  } else if (variant == 6) {   // eight wavefronts, mixed tiling
+    const int64_t tiles = (n + 15) / 16 + m.S;
+    hipLaunchKernelGGL((k_mlp_split8<K0, N1, N2, N3, BF16, 2, true>), dim3((unsigned)tiles), dim3(512), 0, st, a,
+                       m.celu_alpha);
+  } else if (variant == 7) {   // eight wavefronts, 32 atoms per workgroup
+    const int64_t tiles = (n + 31) / 32 + m.S;
+    hipLaunchKernelGGL((k_mlp_split8<K0, N1, N2, N3, BF16, 2, false>), dim3((unsigned)tiles), dim3(512), 0, st, a,
+                       m.celu_alpha);
   } else if (variant == 4) {   // row split, 32 atoms per workgroup, 16 for the smallest species
     const int64_t tiles = (n + 15) / 16 + m.S;
     hipLaunchKernelGGL((k_mlp_mixed<K0, N1, N2, N3, BF16>), dim3((unsigned)tiles), dim3(256), 0, st, a,
@@ -717,8 +739,8 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   const bool bf = m.prec == NNP_BF16;
   const int v = mlp_variant(m, n);
-  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 ? 2 : 1);
-  m.mlp_mixed = v == 4;
+  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 || v == 6 || v == 7 ? 2 : 1);
+  m.mlp_mixed = v == 4 || v == 6;
   switch (m.net_kind) {
     case 0:
       return bf ? run_mlp<128, 160, 128, 96, true>(m, a, n, v, st) : run_mlp<128, 160, 128, 96, false>(m, a, n, v, st);

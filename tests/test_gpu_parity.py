@@ -290,7 +290,7 @@ def test_autotune_keeps_results(P, w_water):
         torch.cuda.synchronize()
         E0, F0 = E0.clone(), F0.clone()
         chosen = m.autotune(3)
-        assert chosen["network"] in (0, 1, 2, 3, 4) and chosen["neighbours"] in (0, 1, 2, 3)
+        assert 0 <= chosen["network"] < 8 and chosen["neighbours"] in (0, 1, 2, 3)
         assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1)
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
@@ -304,8 +304,10 @@ def test_autotune_keeps_results(P, w_water):
 VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours", 2, "fp32"),
             ("neighbours", 3, "fp32"), ("descriptor", 0, "fp32"), ("descriptor", 2, "fp32"),
             ("descriptor", 1, "fp32"), ("network", 0, "fp32"), ("network", 1, "fp32"), ("network", 2, "fp32"),
-            ("network", 3, "fp32"), ("network", 4, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"),
-            ("network", 2, "bf16"), ("network", 3, "bf16"), ("network", 4, "bf16"), ("adjoint", 0, "fp32"),
+            ("network", 3, "fp32"), ("network", 4, "fp32"), ("network", 5, "fp32"), ("network", 6, "fp32"),
+            ("network", 7, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
+            ("network", 3, "bf16"), ("network", 4, "bf16"), ("network", 5, "bf16"), ("network", 6, "bf16"),
+            ("network", 7, "bf16"), ("adjoint", 0, "fp32"),
             ("adjoint", 1, "fp32")]
 
 
@@ -330,7 +332,7 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    nvar = {"network": 5, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
+    nvar = {"network": 8, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
     for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
@@ -378,7 +380,7 @@ def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
     same whichever kernel ran."""
     pos, Z, box = boxes["c2"]
     ref = None
-    for v in range(5):
+    for v in range(8):
         m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision=prec)
         m.set_variant("network", v)
         F = _run(m, pos, Z, box)[1]
