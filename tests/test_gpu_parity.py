@@ -390,6 +390,42 @@ def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
         assert np.array_equal(F, ref), f"network variant {v}"
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_network_variants_bitwise_forces_wide(P, w_hcno, prec):
+    """The same bitwise agreement for the wide H/C/N/O networks: the batched
+    walk molecules (384 inputs) and the solute with the MM channel (416 after
+    padding), including the MM forces."""
+    pos, Z, off = sy.walk_batch(24, seed=9)
+    d = torch.from_numpy(pos).cuda()
+    ref = None
+    for v in range(8):
+        m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision=prec)
+        m.set_variant("network", v)
+        E, F = m.compute_batch(d, Z, off)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        F = F.cpu().numpy()
+        m.close()
+        if ref is None:
+            ref = F
+        assert np.array_equal(F, ref), f"network variant {v}"
+    sysd = sy.solute_in_water(seed=0)
+    w = sy.model_weights(HCNO_MM, seed=3)
+    mm_pos, mm_q = torch.from_numpy(sysd["mm_pos"]).cuda(), torch.from_numpy(sysd["mm_q"]).cuda()
+    ref = None
+    for v in range(8):
+        m = P.NNPModel(HCNO_MM, weights=sy.flat_weights(w), precision=prec)
+        m.set_variant("network", v)
+        _, F, Fmm = _run(m, sysd["pos"], sysd["Z"], sysd["box"], mm_pos=mm_pos, mm_q=mm_q)
+        m.close()
+        if ref is None:
+            ref = (F, Fmm)
+        # forces on the NNP atoms are bitwise equal; MM forces are FP64 sums in
+        # atomic order, so equal to rounding
+        assert np.array_equal(F, ref[0]), f"network variant {v}"
+        assert np.allclose(Fmm, ref[1], rtol=0, atol=1e-12 * max(1.0, np.abs(ref[1]).max())), f"variant {v}"
+
+
 def test_neighbour_sets_batched_and_open(P, w_hcno):
     pos, Z, off = sy.walk_batch(6, seed=7)
     m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
