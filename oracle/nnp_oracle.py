@@ -39,7 +39,7 @@ import torch
 
 __all__ = [
     "species_index", "pair_class_table", "neighbour_pairs", "neighbour_pairs_bruteforce",
-    "cutoff", "celu", "descriptors", "mlp_energies", "mlp_input_grad", "evaluate",
+    "cutoff", "celu", "descriptors", "mlp_outputs", "mlp_energies", "mlp_input_grad", "evaluate",
     "evaluate_batch", "cell_list_fp32", "neighbours_fp32", "mm_potential", "link_atom_positions",
     "me_coupling",
 ]
@@ -293,9 +293,10 @@ def _as_t(a):
     return torch.as_tensor(np.asarray(a, np.float64))
 
 
-def mlp_energies(x, sigma_c, weights, alpha):
-    """e_i = W4 h3 + b4 with h_l = CELU(W_l h_{l-1} + b_l), one network per species."""
-    e = torch.zeros(x.shape[0], dtype=torch.float64)
+def mlp_outputs(x, sigma_c, weights, alpha):
+    """[rows, n_out] = W4 h3 + b4 with h_l = CELU(W_l h_{l-1} + b_l), one network per species."""
+    n_out = len(weights[0][-1][1])
+    o = torch.zeros((x.shape[0], n_out), dtype=torch.float64)
     sigma_c = np.asarray(sigma_c)
     for s, layers in enumerate(weights):
         rows = np.nonzero(sigma_c == s)[0]
@@ -306,8 +307,20 @@ def mlp_energies(x, sigma_c, weights, alpha):
             h = h @ _as_t(W).T + _as_t(b)
             if l < len(layers) - 1:
                 h = celu(h, float(alpha))
-        e = e.index_put((torch.tensor(rows),), h[:, 0])
-    return e
+        o = o.index_put((torch.tensor(rows),), h)
+    return o
+
+
+def mlp_energies(x, sigma_c, weights, alpha):
+    """Atomic energies.  One output: e_i.  Two outputs (models with the MM
+    potential as last input): the second is a predicted atomic charge q_i in
+    the MM potential phi_i, e_i + q_i phi_i -- electrostatic embedding with
+    charges from the model (Methods: the model may return charges / put
+    forces on MM atoms)."""
+    o = mlp_outputs(x, sigma_c, weights, alpha)
+    if o.shape[1] == 1:
+        return o[:, 0]
+    return o[:, 0] + o[:, 1] * x[:, -1]
 
 
 def mlp_input_grad(x_np, sigma_c, weights, alpha):

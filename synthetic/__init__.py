@@ -53,17 +53,20 @@ def model_config(kind: str = "water") -> dict:
     kind: "water"  -- species {H, O}, 128-dim descriptor, 128-160-128-96-1 MLP;
           "hcno"   -- species {H, C, N, O}, 384-dim descriptor, 384-256-192-160-1;
           "hcno_mm"-- as "hcno" plus one extra input (the MM electrostatic
-                      potential at the atom), 385-256-192-160-1.
+                      potential at the atom), 385-256-192-160-1;
+          "hcno_ee"-- as "hcno_mm" with a second output, a predicted atomic
+                      charge q_i that enters as q_i phi_i, 385-256-192-160-2.
     """
     if kind == "water":
         species = (1, 8)
-    elif kind in ("hcno", "hcno_mm"):
+    elif kind in ("hcno", "hcno_mm", "hcno_ee"):
         species = (1, 6, 7, 8)
     else:
         raise ValueError(f"unknown model kind {kind!r}")
     S = len(species)
     D = 16 * S + 32 * (S * (S + 1) // 2)
-    extra = 1 if kind == "hcno_mm" else 0
+    extra = 1 if kind in ("hcno_mm", "hcno_ee") else 0
+    n_out = 2 if kind == "hcno_ee" else 1
     hidden = (160, 128, 96) if kind == "water" else (256, 192, 160)
     f32 = np.float32
     return {
@@ -77,7 +80,7 @@ def model_config(kind: str = "water") -> dict:
         "rad_shift": np.linspace(0.9, 5.2, 16).astype(f32),
         "ang_shift": np.linspace(0.9, 3.5, 8).astype(f32),
         "ang_sect": ((2 * np.arange(4) + 1) * math.pi / 8).astype(f32),
-        "widths": (D + extra,) + hidden + (1,),
+        "widths": (D + extra,) + hidden + (n_out,),
         "celu_alpha": f32(0.1),
         "extra_inputs": extra,
         "mm_cutoff": f32(12.0),

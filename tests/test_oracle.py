@@ -20,6 +20,7 @@ mpmath.mp.dps = 30
 WATER = sy.model_config("water")
 HCNO = sy.model_config("hcno")
 HCNO_MM = sy.model_config("hcno_mm")
+HCNO_EE = sy.model_config("hcno_ee")
 
 
 @pytest.fixture(scope="module")
@@ -155,6 +156,89 @@ def test_mm_channel_single_charge_closed_form():
     assert x.shape == (1, 385)
     assert abs(x[0, -1] - float(phi)) < 1e-13 * abs(float(phi))
     assert np.all(x[0, :-1] == 0.0)
+
+
+def _constant_output_weights(cfg, e0, q0):
+    """Every W and hidden bias zero, output bias (e0, q0): h3 = CELU(0) = 0, so
+    e_i = e0 and q_i = q0 for every atom."""
+    w = sy.model_weights(cfg, seed=1)
+    out = []
+    for layers in w[0]:
+        new = [(np.zeros_like(W), np.zeros_like(b)) for W, b in layers]
+        new[-1] = (new[-1][0], np.array([e0, q0], np.float32))
+        out.append(new)
+    return [out]
+
+
+def test_charge_head_single_charge_closed_form():
+    """Predicted charge q in the MM potential: E = e0 + q0 phi with
+    phi = ke Q fc(r; 12)/r; the force on the ML atom is q0 ke Q f'(r) u (u the
+    unit vector to the MM atom, f = fc/r) and the MM atom feels the opposite."""
+    e0, q0 = 0.25, -0.375
+    w = _constant_output_weights(HCNO_EE, e0, q0)
+    pos = np.array([[10.0, 10.0, 10.0]])
+    Z = np.array([6])
+    mm_pos = np.array([[13.0, 11.0, 9.5]])
+    Q = -0.834
+    ref = orc.evaluate(pos, Z, HCNO_EE, w, box=None, mm_pos=mm_pos, mm_q=np.array([Q]))
+    d = [mpmath.mpf(3), mpmath.mpf(1), mpmath.mpf("-0.5")]
+    r = mpmath.sqrt(sum(a * a for a in d))
+    R = mpmath.mpf(12)
+    ke = mpmath.mpf(sy.KE_COULOMB)
+    fc = mp_fc(r, R)
+    E = _mp(np.float32(e0)) + _mp(np.float32(q0)) * ke * _mp(Q) * fc / r
+    dfc = -mpmath.pi / (2 * R) * mpmath.sin(mpmath.pi * r / R)
+    fprime = (dfc * r - fc) / (r * r)
+    F = [_mp(np.float32(q0)) * ke * _mp(Q) * fprime * a / r for a in d]
+    assert abs(ref["E"] - float(E)) < 1e-13 * abs(float(E))
+    for k in range(3):
+        assert abs(ref["F"][0, k] - float(F[k])) < 1e-12 * max(1.0, abs(float(F[k])))
+        assert abs(ref["F_mm"][0, k] + float(F[k])) < 1e-12 * max(1.0, abs(float(F[k])))
+
+
+def test_charge_head_reduces_to_energy_only_model():
+    """With the charge row of the output layer zero the two-output model is the
+    one-output model with the same other weights."""
+    sys_ = sy.solute_in_water(seed=0, n_solute=12, n_side=8, L=24.8, n_keep=300)
+    w_ee = sy.model_weights(HCNO_EE, seed=3)
+    w_mm = [[[*layers[:-1], (layers[-1][0][:1].copy(), layers[-1][1][:1].copy())] for layers in mem]
+            for mem in w_ee]
+    for mem in w_ee:
+        for layers in mem:
+            layers[-1][0][1] = 0.0
+            layers[-1][1][1] = 0.0
+    args = dict(box=sys_["box"], mm_pos=sys_["mm_pos"], mm_q=sys_["mm_q"])
+    a = orc.evaluate(sys_["pos"], sys_["Z"], HCNO_EE, w_ee, **args)
+    b = orc.evaluate(sys_["pos"], sys_["Z"], HCNO_MM, w_mm, **args)
+    assert abs(a["E"] - b["E"]) < 1e-12 * abs(b["E"])
+    np.testing.assert_allclose(a["F"], b["F"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a["F_mm"], b["F_mm"], rtol=0, atol=1e-12)
+
+
+def test_charge_head_forces_fd():
+    """Central differences of E for NNP and MM atoms with the charge head (the
+    q_i phi_i term couples both networks' outputs and the MM geometry)."""
+    sys_ = sy.solute_in_water(seed=0, n_solute=12, n_side=8, L=24.8, n_keep=300)
+    w = sy.model_weights(HCNO_EE, seed=3)
+    args = dict(box=sys_["box"], mm_pos=sys_["mm_pos"].astype(np.float64), mm_q=sys_["mm_q"])
+    pos = sys_["pos"].astype(np.float64)
+    ref = orc.evaluate(pos, sys_["Z"], HCNO_EE, w, **args)
+    assert np.abs(ref["F"].sum(0) + ref["F_mm"].sum(0)).max() < 1e-10
+    h = 1e-4
+    for a in (0, 7):
+        for k in range(3):
+            p1 = pos.copy(); p1[a, k] += h
+            p2 = pos.copy(); p2[a, k] -= h
+            fd = -(orc.evaluate(p1, sys_["Z"], HCNO_EE, w, forces=False, **args)["E"]
+                   - orc.evaluate(p2, sys_["Z"], HCNO_EE, w, forces=False, **args)["E"]) / (2 * h)
+            assert abs(fd - ref["F"][a, k]) < 2e-7 * max(1.0, abs(ref["F"][a, k]))
+    j = int(np.argmax(np.abs(ref["F_mm"]).sum(1)))
+    for k in range(3):
+        m1 = args["mm_pos"].copy(); m1[j, k] += h
+        m2 = args["mm_pos"].copy(); m2[j, k] -= h
+        e1 = orc.evaluate(pos, sys_["Z"], HCNO_EE, w, forces=False, **{**args, "mm_pos": m1})["E"]
+        e2 = orc.evaluate(pos, sys_["Z"], HCNO_EE, w, forces=False, **{**args, "mm_pos": m2})["E"]
+        assert abs(-(e1 - e2) / (2 * h) - ref["F_mm"][j, k]) < 2e-7 * max(1.0, abs(ref["F_mm"][j, k]))
 
 
 # ------------------------------------------------------------- library routines
