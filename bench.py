@@ -44,6 +44,9 @@ WORKLOADS = {
     "c5b": dict(kind="solute_mm",
                 desc="60-atom H/C/N/O walk solute in 10,000 fixed-charge MM waters (30,000 point charges "
                      "entering as the extra input channel, 12 A), periodic L=68.3 A"),
+    "c5e": dict(kind="solute_ee",
+                desc="60-atom H/C/N/O walk solute in 10,000 fixed-charge MM waters, electrostatic embedding "
+                     "with network-predicted atomic charges (E_i = e_i + q_i phi_i), periodic L=68.3 A"),
 }
 
 # Peaks (MI355X, published): HBM 8 TB/s; dense MFMA FP32 157.3 TFLOP/s, BF16 2.5 PFLOP/s.
@@ -69,7 +72,7 @@ OPS_MM_BWD_PAIR = 80
 
 # rocprofv3 summaries committed under profiles/ (written by --summarize-profiles).
 PROFILE_TAGS = {"c1": "water192", "c2": "water12288", "c3": "water98304", "c5a": "water261000",
-                "c4": "hcno_batch256", "c5b": "hcno60_mm30000"}
+                "c4": "hcno_batch256", "c5b": "hcno60_mm30000", "c5e": "hcno60_mm30000_charges"}
 CSRC = os.path.join(ROOT, "paper_2604_21441_amd", "csrc")
 CALIB_BYTES = 1 << 30   # --calib-copy: one device copy of this many bytes (read + write)
 
@@ -109,6 +112,10 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
     if stage == "network":
         nv = v.get("network", 2)
         dims = f"{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {bf}"
+        if widths[-1] == 2:   # charge output: one kernel template, (columns, mixed, wavefronts) per variant
+            c, mixed, nw = {2: (2, False, 4), 3: (2, False, 4), 4: (2, True, 4), 5: (1, False, 8),
+                            6: (2, True, 8), 7: (2, False, 8)}.get(nv, (1, False, 4))
+            return f"k_mlp_split_q<{dims}, {c}, {'true' if mixed else 'false'}, {nw}>"
         cols = {1: 1, 2: 2, 3: 4 if k0 <= 128 else 2}.get(nv)
         if nv == 4:
             return f"k_mlp_mixed<{dims}>"
@@ -233,9 +240,10 @@ def summarize_profiles(out_dir, workload):
 
 
 def network_flops_per_atom(widths):
-    """2 x multiply-adds of the forward chain plus the three backward products."""
+    """2 x multiply-adds of the forward chain (one output row, or two with a charge
+    output) plus the three backward products."""
     K0, N1, N2, N3 = widths[0], widths[1], widths[2], widths[3]
-    fwd = K0 * N1 + N1 * N2 + N2 * N3 + N3
+    fwd = K0 * N1 + N1 * N2 + N2 * N3 + N3 * widths[4]
     bwd = N3 * N2 + N2 * N1 + N1 * K0
     return 2 * (fwd + bwd)
 
@@ -248,8 +256,8 @@ def build_inputs(name):
         cfg = sy.model_config("water")
         pos, Z, box = sy.water_box(w["n_mol"], w["L"], seed=0)
         return cfg, dict(pos=pos, Z=Z, box=box, offsets=None, mm_pos=None, mm_q=None)
-    if w["kind"] == "solute_mm":
-        cfg = sy.model_config("hcno_mm")
+    if w["kind"] in ("solute_mm", "solute_ee"):
+        cfg = sy.model_config("hcno_mm" if w["kind"] == "solute_mm" else "hcno_ee")
         s = sy.solute_in_water(seed=0)
         return cfg, dict(pos=s["pos"], Z=s["Z"], box=s["box"], offsets=None, mm_pos=s["mm_pos"], mm_q=s["mm_q"])
     cfg = sy.model_config("hcno")

@@ -82,7 +82,12 @@ typedef enum { NNP_FP32 = 0, NNP_BF16 = 1 } nnp_precision;
  * extra_inputs = 1 the MM potential phi_i = ke_coulomb sum_j q_j fc(r_ij;
  * mm_cutoff) / r_ij is appended as the last input.
  * Network per species: h_l = CELU_alpha(W_l h_{l-1} + b_l) for the hidden
- * layers, e_i = W_L h_{L-1} + b_L (linear output).
+ * layers, e_i = W_L h_{L-1} + b_L (linear output).  With extra_inputs = 1 the
+ * output layer may have two rows (widths[4] = 2): the second is a predicted
+ * atomic charge q_i, and the atomic energy is e_i + q_i phi_i -- electrostatic
+ * embedding with charges from the model (Methods: the model may return
+ * charges and put forces on MM atoms); the forces then include the
+ * dependence of q_i on the positions through the network.
  * Supported: 1..4 species; 16 radial shifts, 8 angular shifts, 4 angle
  * sections; widths {128,160,128,96,1} (water model) or {384(+1),256,192,160,1}
  * (H/C/N/O model); n_members >= 1 networks averaged (an ensemble sharing one
@@ -99,7 +104,8 @@ typedef struct {
   const float* ang_sect_host;         /* [n_ang_sect] section centres (radians)    */
   int32_t n_layers;                   /* number of entries in widths (5)           */
   const int32_t* widths_host;         /* [n_layers]; widths[0] = descriptor length
-                                         + extra_inputs, widths[n_layers-1] = 1    */
+                                         + extra_inputs, widths[n_layers-1] = 1,
+                                         or 2 (energy, charge) with extra_inputs */
   float celu_alpha;
   int32_t extra_inputs;               /* 0, or 1 for the MM potential channel      */
   float mm_cutoff;                    /* cutoff of the MM potential channel        */
@@ -237,9 +243,11 @@ typedef enum {
   NNP_BUF_ATOM_ENERGY = 7,/* float [n_nnp] atomic energies per sorted slot        */
   NNP_BUF_DEDX = 8,       /* float [n_nnp][row stride] dE/d(descriptor) per slot  */
   NNP_BUF_GRID = 9,       /* int32 [4]: n_bins, cells per dimension x, y, z      */
-  NNP_BUF_ORDER = 10      /* int32 [n_nnp]: slots in the order the per-atom
+  NNP_BUF_ORDER = 10,     /* int32 [n_nnp]: slots in the order the per-atom
                              kernels visit them: bin by bin, species by species
                              within a bin, ascending slot within a species     */
+  NNP_BUF_CHARGE = 11     /* float [n_nnp] predicted atomic charges per sorted
+                             slot (models with a charge output; else EINVAL)  */
 } nnp_buffer;
 
 /*

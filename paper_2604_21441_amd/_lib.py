@@ -37,6 +37,7 @@ NNP_BUF_ATOM_ENERGY = 7
 NNP_BUF_DEDX = 8
 NNP_BUF_GRID = 9
 NNP_BUF_ORDER = 10
+NNP_BUF_CHARGE = 11
 
 # nnp_stage
 STAGES = ["cells", "neighbours", "descriptor", "mm", "network", "energy", "adjoint", "gather", "mm_adjoint"]

@@ -125,7 +125,7 @@ void free_workspace(nnp_model* m) {
   dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_rank); dfree(m->d_spos);
   dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_loc); dfree(m->d_islot); dfree(m->d_pcount); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
-  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi);
+  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi); dfree(m->d_q);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
   m->h_stage = nullptr;
   m->reserved = false;
@@ -237,8 +237,10 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
   if (prec != NNP_FP32 && prec != NNP_BF16) return set_error(NNP_EINVAL, "unknown precision");
   const int D = descriptor_length(S);
   std::vector<int> w(cfg->widths_host, cfg->widths_host + 5);
-  if (w[0] != D + cfg->extra_inputs || w[4] != 1)
-    return set_error(NNP_EINVAL, "widths[0] must equal the descriptor length plus extra_inputs, widths[4] = 1");
+  if (w[0] != D + cfg->extra_inputs || !(w[4] == 1 || (w[4] == 2 && cfg->extra_inputs == 1)))
+    return set_error(NNP_EINVAL,
+                     "widths[0] must equal the descriptor length plus extra_inputs; widths[4] = 1, or 2 (energy "
+                     "and a predicted charge) with the MM potential channel");
   int kind = -1, stride = 0;
   if (w[1] == 160 && w[2] == 128 && w[3] == 96 && D == 128 && cfg->extra_inputs == 0) {
     kind = 0; stride = 128;
@@ -258,6 +260,7 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
   m->P = S * (S + 1) / 2;
   m->D = D;
   m->extra = cfg->extra_inputs;
+  m->charges = w[4] == 2;
   m->Din = D + cfg->extra_inputs;
   m->stride = stride;
   m->n_members = cfg->n_members;
@@ -384,6 +387,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_g, n * m->stride));
   chk(dalloc(&m->d_e, n));
   chk(dalloc(&m->d_phi, n));
+  if (m->charges) chk(dalloc(&m->d_q, n));
   if (e == hipSuccess) e = hipMemset(m->d_bin_count, 0, (size_t)m->max_bins * sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->d_x, 0, n * m->stride * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->d_g, 0, n * m->stride * sizeof(float));
@@ -724,6 +728,11 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
     case NNP_BUF_NBR_ANG: src = m->d_nbr_ang; count = (int64_t)n * m->max_ang; stride = m->max_ang; break;
     case NNP_BUF_DESCRIPTOR: src = m->d_x; count = (int64_t)n * m->stride; stride = m->stride; break;
     case NNP_BUF_ATOM_ENERGY: src = m->d_e; count = n; break;
+    case NNP_BUF_CHARGE:
+      if (!m->charges) return set_error(NNP_EINVAL, "the model has no charge output");
+      src = m->d_q;
+      count = n;
+      break;
     case NNP_BUF_DEDX: src = m->d_g; count = (int64_t)n * m->stride; stride = m->stride; break;
     case NNP_BUF_NBR_COUNT: {
       std::vector<int> ro((size_t)n * (m->S + 1)), ao((size_t)n * (m->S + 1));

@@ -202,17 +202,23 @@ __device__ __forceinline__ void gemm_lds(const void* __restrict__ W, const v4f* 
   }
 }
 
-template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED, int NW>
+// CHG: the network has a second output, an atomic charge q_i in the MM
+// potential phi_i (input column phi_col): the atomic energy is e_i + q_i phi_i,
+// the backward seed of the last hidden layer is (w_e + phi_i w_q), and q_i is
+// written out for the MM adjoint (dE/dphi_i gets the direct term q_i).
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED, int NW, bool CHG>
 __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   constexpr int oF1 = 0, oF2 = oF1 + N1 * K0, oF3 = oF2 + N2 * N1;
   constexpr int oB1 = oF3 + N3 * N2, oB2 = oB1 + K0 * N1, oB3 = oB2 + N1 * N2;
   constexpr int ob1 = 0, ob2 = ob1 + N1, ob3 = ob2 + N2, ow4 = ob3 + N3, ob4 = ow4 + N3;
+  constexpr int owq = ob4 + 4, obq = owq + N3;   // charge row (CHG)
   constexpr int TX = (K0 > N2 ? K0 : N2) / 16;        // tiles of buffer X (x, then H2, then delta2)
   constexpr int TA = (N1 > N3 ? N1 : N3) / 16;        // tiles of buffer A (H1, then delta3, then delta1)
   using Elem = typename std::conditional<BF16, __bf16, float>::type;
   __shared__ v4f bufX[C * TX * (BF16 ? 32 : 64)];   // BF16 tiles take half the space
   __shared__ v4f bufA[C * TA * (BF16 ? 32 : 64)];
   __shared__ float epart[NW][C * 16];
+  __shared__ float qpart[CHG ? NW : 1][C * 16];
 
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -240,9 +246,18 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
   const float inv_alpha = 1.f / alpha;
   const float inv_alpha_l2 = kLog2e / alpha;
 
-  float e_acc[C];
+  float e_acc[C], q_acc[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) e_acc[c] = 0.f;
+  for (int c = 0; c < C; ++c) e_acc[c] = q_acc[c] = 0.f;
+  float phi[C];   // MM potential of each column's atom (CHG)
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    phi[c] = 0.f;
+    if constexpr (CHG) {
+      const int row = row0 + c * 16 + col;
+      if (row < row_end) phi[c] = a.x[(int64_t)row * a.stride + a.phi_col];
+    }
+  }
 
   for (int mem = 0; mem < a.n_members; ++mem) {
     const Elem* Wm = reinterpret_cast<const Elem*>(a.wmat) + (int64_t)(mem * a.S + s) * a.mat_per_species;
@@ -333,13 +348,16 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
     }
     gemm_lds<N3 / 16, N2, BF16, C, NW>(Wm + oF3, bufX, TX, h3, w, lane, cw);
     float ep[C];
+    float eq[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) ep[c] = 0.f;
+    for (int c = 0; c < C; ++c) ep[c] = eq[c] = 0.f;
 #pragma unroll
     for (int j = 0; j < Own<N3, NW>::n; ++j) {
       const int r = w + NW * j;
       if (r < N3 / 16) {
         const v4f w4 = *reinterpret_cast<const v4f*>(V + ow4 + 16 * r + 4 * q);
+        v4f wq = v4f{0.f, 0.f, 0.f, 0.f};
+        if constexpr (CHG) wq = *reinterpret_cast<const v4f*>(V + owq + 16 * r + 4 * q);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           v4f d;
@@ -347,7 +365,12 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
           for (int t = 0; t < 4; ++t) {
             const float h = celu_f(h3[j][c][t], alpha, inv_alpha_l2);
             ep[c] += w4[t] * h;
-            d[t] = w4[t] * celu_grad_from_h(h, inv_alpha);
+            if constexpr (CHG) {
+              eq[c] += wq[t] * h;
+              d[t] = fmaf(phi[c], wq[t], w4[t]) * celu_grad_from_h(h, inv_alpha);
+            } else {
+              d[t] = w4[t] * celu_grad_from_h(h, inv_alpha);
+            }
           }
           put_tile<BF16>(bufA, TA, c, r, lane, d);
         }
@@ -359,6 +382,12 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
       v += __shfl_xor(v, 16, 64);
       v += __shfl_xor(v, 32, 64);
       if (q == 0) epart[w][c * 16 + col] = v;
+      if constexpr (CHG) {
+        float u = eq[c];
+        u += __shfl_xor(u, 16, 64);
+        u += __shfl_xor(u, 32, 64);
+        if (q == 0) qpart[w][c * 16 + col] = u;
+      }
     }
     __syncthreads();
     if (w == 0) {
@@ -368,7 +397,16 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
         float e = 0.f;
 #pragma unroll
         for (int u = 0; u < NW; ++u) e += epart[u][c * 16 + col];
-        e_acc[c] += e + V[ob4];
+        e += V[ob4];
+        if constexpr (CHG) {
+          float qa = 0.f;
+#pragma unroll
+          for (int u = 0; u < NW; ++u) qa += qpart[u][c * 16 + col];
+          qa += V[obq];
+          e = fmaf(qa, phi[c], e);
+          q_acc[c] += qa;
+        }
+        e_acc[c] += e;
       }
     }
 
@@ -453,6 +491,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
       const float e_atom = e_acc[c] / (float)a.n_members;
       if (row < row_end && q == 0) {
         a.e[row] = e_atom;
+        if constexpr (CHG) a.q[row] = q_acc[c] / (float)a.n_members;
         ev += (double)e_atom;
       }
     }
@@ -466,7 +505,7 @@ __device__ __forceinline__ void mlp_split_body(const MlpArgs& a, float alpha) {
 
 template <int K0, int N1, int N2, int N3, bool BF16, int C>
 __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a, float alpha) {
-  mlp_split_body<K0, N1, N2, N3, BF16, C, false, 4>(a, alpha);
+  mlp_split_body<K0, N1, N2, N3, BF16, C, false, 4, false>(a, alpha);
 }
 
 // Eight wavefronts per 16-atom tile: each owns half as many row tiles of
@@ -474,7 +513,7 @@ __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_split(MlpArgs a,
 // tiles to fill the GPU (a small ML region: a tile per species).
 template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED>
 __global__ __launch_bounds__(512) void k_mlp_split8(MlpArgs a, float alpha) {
-  mlp_split_body<K0, N1, N2, N3, BF16, C, MIXED, 8>(a, alpha);
+  mlp_split_body<K0, N1, N2, N3, BF16, C, MIXED, 8, false>(a, alpha);
 }
 
 // Mixed tiling: tiles of 32 atoms, of 16 for the species with the fewest
@@ -484,7 +523,13 @@ __global__ __launch_bounds__(512) void k_mlp_split8(MlpArgs a, float alpha) {
 // in the uniform tiling.
 template <int K0, int N1, int N2, int N3, bool BF16>
 __global__ __launch_bounds__(256, K0 <= 128 ? 2 : 1) void k_mlp_mixed(MlpArgs a, float alpha) {
-  mlp_split_body<K0, N1, N2, N3, BF16, 2, true, 4>(a, alpha);
+  mlp_split_body<K0, N1, N2, N3, BF16, 2, true, 4, false>(a, alpha);
+}
+
+// The same kernels for networks with the charge output (MM channel models).
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_mlp_split_q(MlpArgs a, float alpha) {
+  mlp_split_body<K0, N1, N2, N3, BF16, C, MIXED, NW, true>(a, alpha);
 }
 
 // Register-resident variant: each wavefront owns 16 atoms and keeps the whole
@@ -707,6 +752,30 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
   return hipGetLastError();
 }
 
+// Networks with the charge output: the same tilings through k_mlp_split_q.
+// The register-resident kernel has no charge form; variant 0 runs as 1, and
+// the 64-atom tile (narrow networks only) as 2.
+template <int K0, int N1, int N2, int N3, bool BF16, int C, bool MIXED, int NW>
+void launch_q(const MlpArgs& a, int n, int S, float alpha, hipStream_t st) {
+  const int64_t tiles = (C == 2 && !MIXED ? (n + 31) / 32 : (n + 15) / 16) + S;
+  hipLaunchKernelGGL((k_mlp_split_q<K0, N1, N2, N3, BF16, C, MIXED, NW>), dim3((unsigned)tiles), dim3(64 * NW), 0,
+                     st, a, alpha);
+}
+
+template <int K0, int N1, int N2, int N3, bool BF16>
+hipError_t run_mlp_q(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream_t st) {
+  const float al = m.celu_alpha;
+  switch (variant) {
+    case 2: case 3: launch_q<K0, N1, N2, N3, BF16, 2, false, 4>(a, n, m.S, al, st); break;
+    case 4: launch_q<K0, N1, N2, N3, BF16, 2, true, 4>(a, n, m.S, al, st); break;
+    case 5: launch_q<K0, N1, N2, N3, BF16, 1, false, 8>(a, n, m.S, al, st); break;
+    case 6: launch_q<K0, N1, N2, N3, BF16, 2, true, 8>(a, n, m.S, al, st); break;
+    case 7: launch_q<K0, N1, N2, N3, BF16, 2, false, 8>(a, n, m.S, al, st); break;
+    default: launch_q<K0, N1, N2, N3, BF16, 1, false, 4>(a, n, m.S, al, st); break;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Network kernel variant: 0 register-resident (16 atoms per wavefront),
@@ -737,6 +806,8 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.vec_per_species = m.vec_per_species;
   a.status = m.d_status;
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
+  a.q = m.charges ? m.d_q : nullptr;
+  a.phi_col = m.D;   // the MM potential follows the descriptor
   const bool bf = m.prec == NNP_BF16;
   const int v = mlp_variant(m, n);
   m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 || v == 6 || v == 7 ? 2 : 1);
@@ -747,6 +818,9 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
     case 1:
       return bf ? run_mlp<384, 256, 192, 160, true>(m, a, n, v, st) : run_mlp<384, 256, 192, 160, false>(m, a, n, v, st);
     case 2:
+      if (m.charges)
+        return bf ? run_mlp_q<416, 256, 192, 160, true>(m, a, n, v, st)
+                  : run_mlp_q<416, 256, 192, 160, false>(m, a, n, v, st);
       return bf ? run_mlp<416, 256, 192, 160, true>(m, a, n, v, st) : run_mlp<416, 256, 192, 160, false>(m, a, n, v, st);
     default:
       return hipErrorInvalidValue;

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_mm_finish(const double* __restrict__
   if (i < n) x[(int64_t)i * p.stride + p.D] = (float)(p.ke * phi[i]);
 }
 
-// Adjoint: dE/dphi_i = g[i][D];  dphi_i/dy_j = ke q_j f'(r) u,  f(r) = fc(r)/r,
+// Adjoint: dE/dphi_i = g[i][D] (+ the predicted charge q_i of a network with
+// a charge output, whose energy holds q_i phi_i);  dphi_i/dy_j = ke q_j f'(r) u,  f(r) = fc(r)/r,
 // u = (y_j - x_i)/r.  MM atom j gets -sum_i dE/dphi_i dphi_i/dy_j (owned by its
 // lane), NNP atom i gets the opposite of its column sum (wave-reduced, one
 // FP64 atomic per wavefront and atom).
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
                                                    const int* __restrict__ slot_atom, int n,
                                                    const float* __restrict__ mm_pos,
                                                    const float* __restrict__ mm_q, int n_mm,
-                                                   const float* __restrict__ gx, DescParams p, Geometry g,
+                                                   const float* __restrict__ gx,
+                                                   const float* __restrict__ qpred, DescParams p, Geometry g,
                                                    double* __restrict__ forces,
                                                    double* __restrict__ mm_forces,
                                                    double* __restrict__ link_forces) {
@@ -106,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_mm_bwd(const float4* __restrict__ sp
   for (int i = i0; i < i1; ++i) {
     float4 pi = spos[i];
     float gi = gx[(int64_t)i * p.stride + p.D];
+    if (qpred != nullptr) gi += qpred[i];
     float dx, dy, dz, r2;
     mm_disp(pi, yx, yy, yz, g, dx, dy, dz, r2);
     float vx = 0.f, vy = 0.f, vz = 0.f;
@@ -160,8 +163,8 @@ hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, con
                          double* forces, double* mm_forces, hipStream_t st) {
   if (n == 0 || n_mm == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mm_bwd, dim3((n_mm + kBlock - 1) / kBlock, (n + kNnpChunk - 1) / kNnpChunk), dim3(kBlock),
-                     0, st, m.d_spos, m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.dp, m.geo, forces, mm_forces,
-                     m.d_link_F);
+                     0, st, m.d_spos, m.d_slot_atom, n, mm_pos, mm_q, n_mm, m.d_g, m.charges ? m.d_q : nullptr, m.dp,
+                     m.geo, forces, mm_forces, m.d_link_F);
   return hipGetLastError();
 }
 

@@ -122,6 +122,8 @@ struct MlpArgs {
   int64_t vec_per_species; // elements per (member, species) in wvec
   double* part;            // per-wavefront FP64 energy partials, or null
   int* status;
+  float* q;                // predicted atomic charges (output), or null: no charge head
+  int phi_col;             // column of x holding the MM potential (models with charges)
 };
 
 }  // namespace nnp
@@ -131,6 +133,7 @@ struct nnp_model {
   int device = 0;
   nnp_precision prec = NNP_FP32;
   int S = 0, P = 0, D = 0, Din = 0, stride = 0, n_members = 1, extra = 0;
+  int charges = 0;                      // second network output: an atomic charge in the MM potential
   std::vector<int> species;             // atomic numbers, ascending
   std::vector<int> widths;              // unpadded widths
   float celu_alpha = 0.1f;
@@ -184,6 +187,7 @@ struct nnp_model {
   float* d_g = nullptr;
   float* d_e = nullptr;
   double* d_phi = nullptr;     // MM potential accumulator [max_atoms]
+  float* d_q = nullptr;        // predicted atomic charges (member mean) [max_atoms], models with charges
   int* d_status = nullptr;
   int* h_stage = nullptr;      // pinned staging for topology uploads
 

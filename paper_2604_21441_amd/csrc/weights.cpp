@@ -99,7 +99,8 @@ void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<flo
   int64_t mat_elems = (int64_t)N1 * K0p + (int64_t)N2 * N1 + (int64_t)N3 * N2 + (int64_t)K0p * N1 +
                       (int64_t)N1 * N2 + (int64_t)N2 * N3;
   mat_per_species = mat_elems;
-  vec_per_species = N1 + N2 + N3 + N3 + 4;
+  const int n_out = m.charges ? 2 : 1;   // energy, and the predicted charge
+  vec_per_species = N1 + N2 + N3 + n_out * (N3 + 4);
   for (int mem = 0; mem < m.n_members; ++mem)
     for (int s = 0; s < m.S; ++s) {
       const float* W1 = m.w_host.data() + off;
@@ -108,9 +109,9 @@ void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<flo
       const float* b2 = W2 + (size_t)N2 * N1;
       const float* W3 = b2 + N2;
       const float* b3 = W3 + (size_t)N3 * N2;
-      const float* W4 = b3 + N3;
-      const float* b4 = W4 + N3;
-      off = (size_t)(b4 + 1 - m.w_host.data());
+      const float* W4 = b3 + N3;                 // [n_out x N3]
+      const float* b4 = W4 + (size_t)n_out * N3;  // [n_out]
+      off = (size_t)(b4 + n_out - m.w_host.data());
       auto g1 = [&](int r, int c) { return c < K0 ? W1[(size_t)r * K0 + c] : 0.f; };
       auto g2 = [&](int r, int c) { return W2[(size_t)r * N1 + c]; };
       auto g3 = [&](int r, int c) { return W3[(size_t)r * N2 + c]; };
@@ -126,11 +127,13 @@ void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<flo
       vec.insert(vec.end(), b1, b1 + N1);
       vec.insert(vec.end(), b2, b2 + N2);
       vec.insert(vec.end(), b3, b3 + N3);
-      vec.insert(vec.end(), W4, W4 + N3);
-      vec.push_back(b4[0]);
-      vec.push_back(0.f);
-      vec.push_back(0.f);
-      vec.push_back(0.f);
+      for (int o = 0; o < n_out; ++o) {   // output row o: weights, bias, 3 zeros of padding
+        vec.insert(vec.end(), W4 + (size_t)o * N3, W4 + (size_t)(o + 1) * N3);
+        vec.push_back(b4[o]);
+        vec.push_back(0.f);
+        vec.push_back(0.f);
+        vec.push_back(0.f);
+      }
     }
 }
 

@@ -201,7 +201,8 @@ def nnp_read_buffer(h, which: int, stream=None) -> np.ndarray:
     stride = C.c_int32()
     _check(lib.nnp_read_buffer(h, which, None, 0, C.byref(elems), C.byref(stride), _stream(stream)),
            "nnp_read_buffer")
-    dt = np.float32 if which in (L.NNP_BUF_DESCRIPTOR, L.NNP_BUF_ATOM_ENERGY, L.NNP_BUF_DEDX) else np.int32
+    dt = (np.float32 if which in (L.NNP_BUF_DESCRIPTOR, L.NNP_BUF_ATOM_ENERGY, L.NNP_BUF_DEDX, L.NNP_BUF_CHARGE)
+          else np.int32)
     out = np.empty(elems.value, dtype=dt)
     _check(lib.nnp_read_buffer(h, which, out.ctypes.data_as(C.c_void_p), out.nbytes, C.byref(elems),
                                C.byref(stride), _stream(stream)), "nnp_read_buffer")

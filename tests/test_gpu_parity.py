@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 WATER = sy.model_config("water")
 HCNO = sy.model_config("hcno")
 HCNO_MM = sy.model_config("hcno_mm")
+HCNO_EE = sy.model_config("hcno_ee")
 
 
 def _lib():
@@ -578,6 +579,44 @@ def test_mm_charge_channel(P):
     Fall_ref = np.concatenate([ref["F"], ref["F_mm"]])
     assert rel_rmse(Fall, Fall_ref) < 1e-5
     assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_predicted_charge_embedding(P, prec):
+    """Electrostatic embedding with charges from the network (a second output
+    q_i entering as q_i phi_i): energy, NNP and MM forces against the oracle,
+    for every network kernel.  Across kernels the forces agree to rounding
+    only: q_i is a dot product summed over the wavefronts that own the rows,
+    so its FP32 summation order depends on the wavefront count, and q_i
+    reaches the forces through dE/dphi_i."""
+    sysd = sy.solute_in_water(seed=0)
+    w = sy.model_weights(HCNO_EE, seed=3)
+    ref = orc.evaluate(sysd["pos"], sysd["Z"], HCNO_EE, w, box=sysd["box"], mm_pos=sysd["mm_pos"],
+                       mm_q=sysd["mm_q"])
+    mm_pos, mm_q = torch.from_numpy(sysd["mm_pos"]).cuda(), torch.from_numpy(sysd["mm_q"]).cuda()
+    n = len(sysd["Z"])
+    tol_e, tol_f = (1e-6, 1e-5) if prec == "fp32" else (1e-2, 1e-2)
+    x = orc.evaluate(sysd["pos"], sysd["Z"], HCNO_EE, w, box=sysd["box"], mm_pos=sysd["mm_pos"],
+                     mm_q=sysd["mm_q"], forces=False, return_x=True)["x"]
+    sig = orc.species_index(sysd["Z"], HCNO_EE["species"])
+    q_ref = orc.mlp_outputs(torch.tensor(x), sig, w[0], HCNO_EE["celu_alpha"])[:, 1].numpy()
+    first = None
+    for v in range(8):
+        m = P.NNPModel(HCNO_EE, weights=sy.flat_weights(w), precision=prec)
+        m.set_variant("network", v)
+        E, F, Fmm = _run(m, sysd["pos"], sysd["Z"], sysd["box"], mm_pos=mm_pos, mm_q=mm_q)
+        if v == 0:   # the predicted charges themselves, per atom
+            qs = np.empty(n)
+            qs[m.read(P._lib.NNP_BUF_PERM)] = m.read(P._lib.NNP_BUF_CHARGE)
+            np.testing.assert_allclose(qs, q_ref, rtol=0, atol=(1e-5 if prec == "fp32" else 2e-2) * np.abs(q_ref).max())
+        m.close()
+        assert abs(E[0] - ref["E"]) / n < tol_e, (v, E[0], ref["E"])
+        Fall = np.concatenate([F, Fmm])
+        assert rel_rmse(Fall, np.concatenate([ref["F"], ref["F_mm"]])) < tol_f, v
+        assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
+        if first is None:
+            first = F
+        assert rel_rmse(F, first) < 1e-6, f"network variant {v}"
 
 
 # ------------------------------------------------- caller's pair list (Methods)
