@@ -75,7 +75,23 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
   }
   int k = sigma[t] * g.n_bins + bin;
   key[t] = k;
-  rank[t] = atomicAdd(&bin_count[k], 1);   // arrival order among the atoms of the key
+  if (g.periodic) {
+    rank[t] = atomicAdd(&bin_count[k], 1);   // arrival order among the atoms of the key
+    return;
+  }
+  // Open systems (bins are systems): a system's atoms are contiguous, so a
+  // wavefront holds few distinct keys and per-atom atomics would queue on the
+  // same few counters.  One atomic per distinct key and wavefront instead (the
+  // system ranking places the atoms itself; no arrival rank is needed).
+  const int lane = threadIdx.x & 63;
+  uint64_t todo = __builtin_amdgcn_ballot_w64(true);
+  while (todo != 0) {
+    const int leader = __builtin_ctzll(todo);
+    const int lk = __builtin_amdgcn_readlane(k, leader);
+    const uint64_t same = __builtin_amdgcn_ballot_w64(k == lk);
+    if (lane == leader) atomicAdd(&bin_count[lk], (int)__popcll(same));
+    todo &= ~same;
+  }
 }
 
 // Exclusive scans of the bin histogram by one workgroup.
