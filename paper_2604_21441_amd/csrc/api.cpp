@@ -122,7 +122,7 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
 
 void free_workspace(nnp_model* m) {
   dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_sys_off); dfree(m->d_key); dfree(m->d_bin_count);
-  dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_rank); dfree(m->d_spos);
+  dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_rank); dfree(m->d_spos); dfree(m->d_stg);
   dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_loc); dfree(m->d_islot); dfree(m->d_pcount); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
   dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi); dfree(m->d_q);
@@ -370,6 +370,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_islot, n));
   chk(dalloc(&m->d_pcount, n));
   chk(dalloc(&m->d_spos, n));
+  chk(dalloc(&m->d_stg, n));
   chk(dalloc(&m->d_bin_count, (size_t)m->max_bins));
   chk(dalloc(&m->d_bin_start, (size_t)m->max_bins + 1));
   chk(dalloc(&m->d_cmstart, (size_t)m->max_bins));

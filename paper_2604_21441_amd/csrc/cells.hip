@@ -61,11 +61,13 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
                                                   const int* __restrict__ sigma,
                                                   const int* __restrict__ sys, Geometry g, LinkArgs L,
                                                   int* __restrict__ key, int* __restrict__ rank,
+                                                  float4* __restrict__ stg,
                                                   int* __restrict__ bin_count, int* __restrict__ status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const float3 p = nnp_position(pos, idx[t], L, g);
   float x = p.x, y = p.y, z = p.z;
+  if (g.periodic) stg[t] = make_float4(x, y, z, __int_as_float(sigma[t]));   // for the bin sort
   int bin;
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
     atomicOr(status, kStatusNonFinite);
@@ -100,16 +102,25 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
 //   cmstart[bin * S + species]: bin-major order, the order in which the
 //     per-atom kernels visit the slots (all species of a cell or system
 //     together, so neighbouring atoms are processed close in time).
-// Chunks of kScanChunk entries are staged through LDS so that every global
+// Chunks of kScanThreads * PER entries are staged through LDS so that every global
 // load and store is coalesced (per-thread runs of consecutive entries read
 // straight from memory are several times slower); each thread scans
-// kScanPer consecutive entries of the staged chunk.  The histogram itself is
-// left as it is (the bin sort clears it).
+// PER consecutive entries of the staged chunk, PER being the smallest power
+// of two for which one chunk holds the whole histogram (at most 16; larger
+// histograms take several chunks).  Sizing the chunk to the histogram
+// matters: one workgroup does all of this work, and with 16 entries per
+// thread a 1,024-bin scan took 6.8 us.  The histogram itself is left as it
+// is (the bin sort clears it).
 constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 16;
-constexpr int kScanChunk = kScanThreads * kScanPer;
+constexpr int kScanPerMax = 16;
+constexpr int kScanChunk = kScanThreads * kScanPerMax;   // largest chunk
 
-__device__ __forceinline__ int scan_pad(int i) { return i + i / kScanPer; }   // LDS bank spread
+// LDS index of chunk entry i: one pad word after every PER entries, so the
+// per-thread runs start in different banks (stride PER + 1 is odd).
+template <int PER>
+__device__ __forceinline__ int scan_pad(int i) { return PER == 1 ? i : i + i / PER; }
+template <int PER>
+constexpr int scan_lds_words() { return PER == 1 ? kScanThreads : kScanThreads * (PER + 1); }
 
 // Exclusive prefix of v over the workgroup (thread order); *total receives the sum.
 __device__ __forceinline__ int block_exclusive(int v, int* wsum, int* total) {
@@ -140,94 +151,96 @@ __device__ __forceinline__ int block_exclusive(int v, int* wsum, int* total) {
   return ex;
 }
 
-// Scan of the staged chunk buf[0 .. kScanChunk) in place (exclusive, plus carry).
+// Scan of the staged chunk buf[0 .. kScanThreads * PER) in place (exclusive, plus carry).
+template <int PER>
 __device__ __forceinline__ void scan_chunk(int* buf, int* wsum, int* carry) {
-  int v[kScanPer];
+  int v[PER];
   int sum = 0;
 #pragma unroll
-  for (int u = 0; u < kScanPer; ++u) {
-    v[u] = buf[scan_pad(threadIdx.x * kScanPer + u)];
+  for (int u = 0; u < PER; ++u) {
+    v[u] = buf[scan_pad<PER>(threadIdx.x * PER + u)];
     sum += v[u];
   }
   int total;
   int run = block_exclusive(sum, wsum, &total) + *carry;
 #pragma unroll
-  for (int u = 0; u < kScanPer; ++u) {
-    buf[scan_pad(threadIdx.x * kScanPer + u)] = run;
+  for (int u = 0; u < PER; ++u) {
+    buf[scan_pad<PER>(threadIdx.x * PER + u)] = run;
     run += v[u];
   }
   *carry += total;
   __syncthreads();
 }
 
+template <int PER>
 __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ count, int* __restrict__ start,
                                                        int* __restrict__ cmstart, int S, int n_bins) {
   __shared__ int wsum[2 * (kScanThreads / 64) + 1];
-  __shared__ int buf[kScanChunk + kScanChunk / kScanPer];
-  __shared__ int bufc[kScanChunk + kScanChunk / kScanPer];
+  __shared__ int buf[scan_lds_words<PER>()];
+  __shared__ int bufc[scan_lds_words<PER>()];
   const int nb = S * n_bins;
   int carry = 0;
-  if (nb <= kScanChunk) {
+  if (nb <= kScanThreads * PER) {
     // one chunk: the histogram is read once and both scans run from LDS
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x;
-      bufc[scan_pad(i)] = i < nb ? count[i] : 0;
+      bufc[scan_pad<PER>(i)] = i < nb ? count[i] : 0;
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int b = u * kScanThreads + threadIdx.x;
       int t = 0;
 #pragma unroll
       for (int s = 0; s < kMaxSpecies; ++s)
-        if (s < S && b < n_bins) t += bufc[scan_pad(s * n_bins + b)];
-      buf[scan_pad(b)] = t;
+        if (s < S && b < n_bins) t += bufc[scan_pad<PER>(s * n_bins + b)];
+      buf[scan_pad<PER>(b)] = t;
     }
     __syncthreads();
-    scan_chunk(buf, wsum, &carry);
+    scan_chunk<PER>(buf, wsum, &carry);
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int b = u * kScanThreads + threadIdx.x;
       if (b < n_bins) {
-        int r = buf[scan_pad(b)];
+        int r = buf[scan_pad<PER>(b)];
 #pragma unroll
         for (int s = 0; s < kMaxSpecies; ++s)
           if (s < S) {
             cmstart[b * S + s] = r;
-            r += bufc[scan_pad(s * n_bins + b)];
+            r += bufc[scan_pad<PER>(s * n_bins + b)];
           }
       }
     }
     __syncthreads();
     carry = 0;
-    scan_chunk(bufc, wsum, &carry);
+    scan_chunk<PER>(bufc, wsum, &carry);
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x;
-      if (i < nb) start[i] = bufc[scan_pad(i)];
+      if (i < nb) start[i] = bufc[scan_pad<PER>(i)];
     }
     if (threadIdx.x == 0) start[nb] = carry;
     return;
   }
   // bin-major: bin b carries T[b], the sum of its species counts
-  for (int c0 = 0; c0 < n_bins; c0 += kScanChunk) {
+  for (int c0 = 0; c0 < n_bins; c0 += kScanThreads * PER) {
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
       int t = 0;
 #pragma unroll
       for (int s = 0; s < kMaxSpecies; ++s)
         if (s < S && b < n_bins) t += count[s * n_bins + b];
-      buf[scan_pad(i)] = t;
+      buf[scan_pad<PER>(i)] = t;
     }
     __syncthreads();
-    scan_chunk(buf, wsum, &carry);
+    scan_chunk<PER>(buf, wsum, &carry);
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
       if (b < n_bins) {
-        int r = buf[scan_pad(i)];
+        int r = buf[scan_pad<PER>(i)];
 #pragma unroll
         for (int s = 0; s < kMaxSpecies; ++s)
           if (s < S) {
@@ -240,18 +253,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ c
   }
   // species-major
   carry = 0;
-  for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
+  for (int c0 = 0; c0 < nb; c0 += kScanThreads * PER) {
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x;
-      buf[scan_pad(i)] = c0 + i < nb ? count[c0 + i] : 0;
+      buf[scan_pad<PER>(i)] = c0 + i < nb ? count[c0 + i] : 0;
     }
     __syncthreads();
-    scan_chunk(buf, wsum, &carry);
+    scan_chunk<PER>(buf, wsum, &carry);
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x;
-      if (c0 + i < nb) start[c0 + i] = buf[scan_pad(i)];
+      if (c0 + i < nb) start[c0 + i] = buf[scan_pad<PER>(i)];
     }
     __syncthreads();
   }
@@ -271,63 +284,64 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ key,
 // few tens of KB from L2, cheaper than a kernel boundary); workgroup 0 also
 // writes both scans for the later kernels.  Then each thread places one
 // atom at start[key] + rank.
+template <int PER>
 __global__ __launch_bounds__(kScanThreads) void k_scan_scatter(const int* __restrict__ count, int* __restrict__ start,
                                                                int* __restrict__ cmstart, int S, int n_bins,
                                                                const int* __restrict__ key,
                                                                const int* __restrict__ rank, int n,
                                                                int* __restrict__ tmp) {
   __shared__ int wsum[2 * (kScanThreads / 64) + 1];
-  __shared__ int buf[kScanChunk + kScanChunk / kScanPer];
-  __shared__ int bufc[kScanChunk + kScanChunk / kScanPer];
-  const int nb = S * n_bins;   // <= kScanChunk (checked by the launcher)
+  __shared__ int buf[scan_lds_words<PER>()];
+  __shared__ int bufc[scan_lds_words<PER>()];
+  const int nb = S * n_bins;   // <= kScanThreads * PER (checked by the launcher)
   const int t = blockIdx.x * kScanThreads + threadIdx.x;
   const int k = t < n ? key[t] : 0;
   const int rk = t < n ? rank[t] : 0;
 #pragma unroll
-  for (int u = 0; u < kScanPer; ++u) {
+  for (int u = 0; u < PER; ++u) {
     const int i = u * kScanThreads + threadIdx.x;
-    bufc[scan_pad(i)] = i < nb ? count[i] : 0;
+    bufc[scan_pad<PER>(i)] = i < nb ? count[i] : 0;
   }
   __syncthreads();
   int carry = 0;
   if (blockIdx.x == 0) {   // bin-major starts (workgroup-uniform branch)
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int b = u * kScanThreads + threadIdx.x;
       int tot = 0;
 #pragma unroll
       for (int s = 0; s < kMaxSpecies; ++s)
-        if (s < S && b < n_bins) tot += bufc[scan_pad(s * n_bins + b)];
-      buf[scan_pad(b)] = tot;
+        if (s < S && b < n_bins) tot += bufc[scan_pad<PER>(s * n_bins + b)];
+      buf[scan_pad<PER>(b)] = tot;
     }
     __syncthreads();
-    scan_chunk(buf, wsum, &carry);
+    scan_chunk<PER>(buf, wsum, &carry);
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int b = u * kScanThreads + threadIdx.x;
       if (b < n_bins) {
-        int r = buf[scan_pad(b)];
+        int r = buf[scan_pad<PER>(b)];
 #pragma unroll
         for (int s = 0; s < kMaxSpecies; ++s)
           if (s < S) {
             cmstart[b * S + s] = r;
-            r += bufc[scan_pad(s * n_bins + b)];
+            r += bufc[scan_pad<PER>(s * n_bins + b)];
           }
       }
     }
     __syncthreads();
     carry = 0;
   }
-  scan_chunk(bufc, wsum, &carry);   // species-major starts, in place
+  scan_chunk<PER>(bufc, wsum, &carry);   // species-major starts, in place
   if (blockIdx.x == 0) {
 #pragma unroll
-    for (int u = 0; u < kScanPer; ++u) {
+    for (int u = 0; u < PER; ++u) {
       const int i = u * kScanThreads + threadIdx.x;
-      if (i < nb) start[i] = bufc[scan_pad(i)];
+      if (i < nb) start[i] = bufc[scan_pad<PER>(i)];
     }
     if (threadIdx.x == 0) start[nb] = carry;
   }
-  if (t < n) tmp[bufc[scan_pad(k)] + rk] = t;
+  if (t < n) tmp[bufc[scan_pad<PER>(k)] + rk] = t;
 }
 
 // One wavefront per bin: the atomically scattered entries of the bin are
@@ -336,9 +350,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_scatter(const int* __rest
 // each slot's place in the bin-major visiting order.
 __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ start, int n_bins_total,
                                                     const int* __restrict__ tmp,
-                                                    const float* __restrict__ pos,
-                                                    const int* __restrict__ idx,
-                                                    const int* __restrict__ sigma, Geometry g, LinkArgs L,
+                                                    const float4* __restrict__ stg,
+                                                    const int* __restrict__ idx, Geometry g,
                                                     const int* __restrict__ cmstart, int S,
                                                     int* __restrict__ perm,
                                                     float4* __restrict__ spos,
@@ -374,10 +387,8 @@ __global__ __launch_bounds__(kBlock) void k_binsort(const int* __restrict__ star
     sbin[slot] = packed;
     islot[t] = slot;
     pcount[slot] = 0;
-    const int a = idx[t];
-    const float3 p = nnp_position(pos, a, L, g);
-    spos[slot] = make_float4(p.x, p.y, p.z, __int_as_float(sigma[t]));
-    slot_atom[slot] = a;
+    spos[slot] = stg[t];   // staged by k_stage: no second trip through idx and pos
+    slot_atom[slot] = idx[t];
   }
 }
 
@@ -944,6 +955,26 @@ __global__ __launch_bounds__(64) void k_pairs_lists(NeighArgs a, Geometry g, con
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
+// Smallest power of two PER <= kScanPerMax with nb <= kScanThreads * PER
+// (kScanPerMax for larger histograms, which are scanned in several chunks).
+inline int scan_entries_per_thread(int nb) {
+  int per = 1;
+  while (per < kScanPerMax && nb > kScanThreads * per) per *= 2;
+  return per;
+}
+
+template <int PER>
+void launch_scan(nnp_model& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan<PER>, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
+                     m.S, m.geo.n_bins);
+}
+
+template <int PER>
+void launch_scan_scatter(nnp_model& m, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_scatter<PER>, dim3(blocks_for(n, kScanThreads)), dim3(kScanThreads), 0, st,
+                     m.d_bin_count, m.d_bin_start, m.d_cmstart, m.S, m.geo.n_bins, m.d_key, m.d_rank, n, m.d_tmp);
+}
+
 }  // namespace
 
 hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
@@ -952,15 +983,26 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   int nb = m.S * g.n_bins;
   if (n > 0) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
-                       m.d_sigma, m.d_sys, g, L, m.d_key, m.d_rank, m.d_bin_count, m.d_status);
+                       m.d_sigma, m.d_sys, g, L, m.d_key, m.d_rank, m.d_stg, m.d_bin_count, m.d_status);
   }
   const bool fused = n > 0 && g.periodic && nb <= kScanChunk;
+  const int per = scan_entries_per_thread(nb);
   if (fused) {
-    hipLaunchKernelGGL(k_scan_scatter, dim3(blocks_for(n, kScanThreads)), dim3(kScanThreads), 0, st, m.d_bin_count,
-                       m.d_bin_start, m.d_cmstart, m.S, g.n_bins, m.d_key, m.d_rank, n, m.d_tmp);
+    switch (per) {
+      case 1: launch_scan_scatter<1>(m, n, st); break;
+      case 2: launch_scan_scatter<2>(m, n, st); break;
+      case 4: launch_scan_scatter<4>(m, n, st); break;
+      case 8: launch_scan_scatter<8>(m, n, st); break;
+      default: launch_scan_scatter<16>(m, n, st); break;
+    }
   } else {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
-                       m.S, g.n_bins);
+    switch (per) {
+      case 1: launch_scan<1>(m, st); break;
+      case 2: launch_scan<2>(m, st); break;
+      case 4: launch_scan<4>(m, st); break;
+      case 8: launch_scan<8>(m, st); break;
+      default: launch_scan<16>(m, st); break;
+    }
   }
   if (n > 0 && !g.periodic) {
     hipLaunchKernelGGL(k_rank_systems, dim3(g.n_bins), dim3(64), 0, st, m.d_sys_off, g.n_bins, m.S, m.d_bin_start,
@@ -971,7 +1013,7 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
       hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, m.d_key, m.d_rank, n,
                          m.d_bin_start, m.d_tmp);
     hipLaunchKernelGGL(k_binsort, dim3(blocks_for((int64_t)nb * 64, kBlock)), dim3(kBlock), 0, st,
-                       m.d_bin_start, nb, m.d_tmp, pos, m.d_idx, m.d_sigma, g, L, m.d_cmstart, m.S, m.d_perm,
+                       m.d_bin_start, nb, m.d_tmp, m.d_stg, m.d_idx, g, m.d_cmstart, m.S, m.d_perm,
                        m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin, m.d_islot, m.d_pcount, m.d_bin_count);
   }
   return hipGetLastError();

@@ -169,6 +169,7 @@ struct nnp_model {
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
   int* d_rank = nullptr;       // arrival rank of each atom among the atoms of its bin key
   float4* d_spos = nullptr;    // slot -> position (w = species bits)
+  float4* d_stg = nullptr;     // NNP-local atom -> staged position (w = species bits)
   int* d_slot_atom = nullptr;  // slot -> atom index
   int* d_sbin = nullptr;       // slot -> cell coordinates x<<20 | y<<10 | z (periodic) or system
   int* d_loc = nullptr;        // system atom -> NNP-local index or -1 (pair lists)
