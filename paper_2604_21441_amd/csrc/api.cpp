@@ -125,7 +125,7 @@ void free_workspace(nnp_model* m) {
   dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_rank); dfree(m->d_spos); dfree(m->d_stg);
   dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_loc); dfree(m->d_islot); dfree(m->d_pcount); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
   dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
-  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_phi); dfree(m->d_q);
+  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_mm_part); dfree(m->d_q);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
   m->h_stage = nullptr;
   m->reserved = false;
@@ -387,7 +387,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   chk(dalloc(&m->d_x, n * m->stride));
   chk(dalloc(&m->d_g, n * m->stride));
   chk(dalloc(&m->d_e, n));
-  chk(dalloc(&m->d_phi, n));
+  if (m->extra && max_mm > 0) chk(dalloc(&m->d_mm_part, mm_partial_floats(max_atoms, max_mm)));
   if (m->charges) chk(dalloc(&m->d_q, n));
   if (e == hipSuccess) e = hipMemset(m->d_bin_count, 0, (size_t)m->max_bins * sizeof(int));
   if (e == hipSuccess) e = hipMemset(m->d_x, 0, n * m->stride * sizeof(float));

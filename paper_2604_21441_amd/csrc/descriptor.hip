@@ -284,28 +284,6 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
 // half) and the quad swaps xor 2 and xor 1; the pairings are disjoint, so
 // after four steps every lane's values cover all 16 lanes exactly once.
 
-constexpr int kDppMirror = 0x140;
-constexpr int kDppHalfMirror = 0x141;
-constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
-constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-// v[0, 2H) -> v[0, H): keep the half selected by `upper`, add the partner's
-// copy of that half.
-template <int H, int CTRL>
-__device__ __forceinline__ void halve(float* v, bool upper) {
-#pragma unroll
-  for (int e = 0; e < H; ++e) {
-    const float keep = upper ? v[e + H] : v[e];
-    const float send = upper ? v[e] : v[e + H];
-    v[e] = keep + dpp<CTRL>(send);
-  }
-}
-
 // Sum N values over the L = 16 or 8 lanes of a row; lane `sub` ends with
 // totals [sub N/L, (sub+1) N/L) in v[0 .. N/L).  An 8-lane row is half of a
 // DPP row, whose half-mirror pairs lanes across bit 2 within each half.

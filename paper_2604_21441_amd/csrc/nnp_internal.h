@@ -35,6 +35,31 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
+// Cross-lane sums with DPP row permutations (VALU operands, no LDS round
+// trip): mirror (l <-> 15-l), half-mirror (l <-> 7-l within each half) and
+// the quad swaps xor 2 and xor 1 pair the lanes of a 16-lane row disjointly.
+constexpr int kDppMirror = 0x140;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppXor2 = 0x4E;       // quad_perm(2, 3, 0, 1)
+constexpr int kDppXor1 = 0xB1;       // quad_perm(1, 0, 3, 2)
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// One step of a transposing butterfly: v[0, 2H) -> v[0, H), keeping the half
+// selected by `upper` and adding the partner's copy of that half.
+template <int H, int CTRL>
+__device__ __forceinline__ void halve(float* v, bool upper) {
+#pragma unroll
+  for (int e = 0; e < H; ++e) {
+    const float keep = upper ? v[e + H] : v[e];
+    const float send = upper ? v[e] : v[e + H];
+    v[e] = keep + dpp<CTRL>(send);
+  }
+}
+
 // Mixed network tiling: the species with the fewest atoms (lowest index on
 // ties; empty species are skipped) takes tiles of 16 atoms, the others the
 // kernel's full width, so that a small system splits into workgroups of more
@@ -187,7 +212,7 @@ struct nnp_model {
   float* d_x = nullptr;
   float* d_g = nullptr;
   float* d_e = nullptr;
-  double* d_phi = nullptr;     // MM potential accumulator [max_atoms]
+  float* d_mm_part = nullptr;  // MM channel per-workgroup partials [mm_partial_floats(max_atoms, max_mm)]
   float* d_q = nullptr;        // predicted atomic charges (member mean) [max_atoms], models with charges
   int* d_status = nullptr;
   int* h_stage = nullptr;      // pinned staging for topology uploads
@@ -261,6 +286,7 @@ hipError_t launch_force_gather(nnp_model& m, int n, double* forces, int assign, 
                                int accumulate, hipStream_t st);
 
 // mm.hip
+size_t mm_partial_floats(int max_atoms, int max_mm);   // floats of the MM partial buffer
 hipError_t launch_mm_fwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
                          hipStream_t st);
 hipError_t launch_mm_bwd(nnp_model& m, int n, int n_mm, const float* mm_pos, const float* mm_q,
