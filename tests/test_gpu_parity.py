@@ -296,9 +296,13 @@ def test_autotune_keeps_results(P, w_water):
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
         assert m.status() == 0
-        # variants differ only in summation order
-        assert abs(E1.item() - E0.item()) / len(Z) < 1e-6
-        assert rel_rmse(F1.cpu().numpy(), F0.cpu().numpy()) < 1e-5
+        # Variants differ only in summation order.  In the BF16 form a descriptor
+        # value that differs in its last FP32 bit can round to the neighbouring
+        # BF16 network input (2^-8 relative), a few of the 1.6M inputs per call:
+        # force differences of a few 1e-5 (against 7e-3 for BF16 vs the oracle).
+        e_tol, f_tol = (1e-6, 1e-5) if prec == "fp32" else (1e-5, 2e-4)
+        assert abs(E1.item() - E0.item()) / len(Z) < e_tol
+        assert rel_rmse(F1.cpu().numpy(), F0.cpu().numpy()) < f_tol
         m.close()
 
 
