@@ -344,6 +344,103 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_scatter(const int* __rest
   if (t < n) tmp[bufc[scan_pad<PER>(k)] + rk] = t;
 }
 
+// Small periodic systems: the whole cell list in one workgroup, through LDS.
+// LDS histogram atomics give arrival ranks, both scans run in LDS, and each
+// thread then places its own atoms: the stable slot of atom t is the start of
+// its key plus the number of atoms of that key with a smaller index, counted
+// in the key's segment of the arrival-order scatter.  One launch instead of
+// three (binning, scan + scatter, bin sort), with the same outputs bit for
+// bit.  The device histogram is not touched (it stays zero).
+constexpr int kSmallCells = 2048;   // atoms; LDS: 2 padded scan buffers + 2 ints per atom
+static_assert(kSmallCells % kScanThreads == 0, "whole atoms per thread");
+
+template <int PER>
+__global__ __launch_bounds__(kScanThreads) void k_cells_small(const float* __restrict__ pos, int n,
+                                                              const int* __restrict__ idx,
+                                                              const int* __restrict__ sigma, Geometry g,
+                                                              LinkArgs L, int S, int* __restrict__ key,
+                                                              int* __restrict__ bin_start,
+                                                              int* __restrict__ perm, float4* __restrict__ spos,
+                                                              int* __restrict__ slot_atom,
+                                                              int* __restrict__ order, int* __restrict__ sbin,
+                                                              int* __restrict__ islot, int* __restrict__ pcount,
+                                                              int* __restrict__ status) {
+  __shared__ int wsum[2 * (kScanThreads / 64) + 1];
+  __shared__ int hist[scan_lds_words<PER>()];   // counts per key, then species-major starts
+  __shared__ int bmaj[scan_lds_words<PER>()];   // totals per bin, then bin-major starts
+  __shared__ int tmp[kSmallCells];               // atoms of each key in arrival order
+  __shared__ int kr[kSmallCells];                // key | arrival rank << 15
+  const int nb = S * g.n_bins;                   // <= kScanThreads * PER <= 2^14 (checked by the launcher)
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) hist[scan_pad<PER>(u * kScanThreads + tid)] = 0;
+  __syncthreads();
+  // each thread owns atoms tid + u * kScanThreads and keeps their data in registers
+  constexpr int kOwn = kSmallCells / kScanThreads;
+  float3 pp[kOwn];
+  int aa[kOwn], ss[kOwn];
+#pragma unroll
+  for (int u = 0; u < kOwn; ++u) {
+    const int t = u * kScanThreads + tid;
+    if (t >= n) continue;
+    aa[u] = idx[t];
+    ss[u] = sigma[t];
+    pp[u] = nnp_position(pos, aa[u], L, g);
+    int bin = 0;
+    if (!(isfinite(pp[u].x) && isfinite(pp[u].y) && isfinite(pp[u].z)))
+      atomicOr(status, kStatusNonFinite);
+    else
+      bin = cell_of(pp[u].x, pp[u].y, pp[u].z, g);
+    const int k = ss[u] * g.n_bins + bin;
+    key[t] = k;
+    const int r = atomicAdd(&hist[scan_pad<PER>(k)], 1);
+    kr[t] = k | (r << 15);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int b = u * kScanThreads + tid;
+    int tot = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s)
+      if (s < S && b < g.n_bins) tot += hist[scan_pad<PER>(s * g.n_bins + b)];
+    bmaj[scan_pad<PER>(b)] = tot;
+  }
+  __syncthreads();
+  int carry = 0;
+  scan_chunk<PER>(bmaj, wsum, &carry);
+  carry = 0;
+  scan_chunk<PER>(hist, wsum, &carry);
+  auto start_of = [&](int k) { return k < nb ? hist[scan_pad<PER>(k)] : n; };
+  for (int i = tid; i <= nb; i += kScanThreads) bin_start[i] = start_of(i);
+  for (int t = tid; t < n; t += kScanThreads) {
+    const int v = kr[t];
+    tmp[start_of(v & 0x7fff) + (v >> 15)] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kOwn; ++u) {
+    const int t = u * kScanThreads + tid;
+    if (t >= n) continue;
+    const int k = kr[t] & 0x7fff;
+    const int b0 = start_of(k), b1 = start_of(k + 1);
+    int rank = 0;
+    for (int e = b0; e < b1; ++e) rank += tmp[e] < t;
+    const int slot = b0 + rank;
+    const int sp = k / g.n_bins, bin = k - sp * g.n_bins;
+    int o0 = bmaj[scan_pad<PER>(bin)];   // bin-major: earlier bins, then earlier species of this bin
+    for (int s = 0; s < sp; ++s) o0 += start_of(s * g.n_bins + bin + 1) - start_of(s * g.n_bins + bin);
+    const int cz = bin % g.nc[2], cxy = bin / g.nc[2];
+    perm[slot] = t;
+    order[o0 + rank] = slot;
+    sbin[slot] = ((cxy / g.nc[1]) << 20) | ((cxy % g.nc[1]) << 10) | cz;
+    islot[t] = slot;
+    pcount[slot] = 0;
+    spos[slot] = make_float4(pp[u].x, pp[u].y, pp[u].z, __int_as_float(ss[u]));
+    slot_atom[slot] = aa[u];
+  }
+}
+
 // One wavefront per bin: the atomically scattered entries of the bin are
 // ranked by atom index (a stable order independent of the atomic order), and
 // the sorted positions / species / atom indices are written per slot, and
@@ -970,6 +1067,13 @@ void launch_scan(nnp_model& m, hipStream_t st) {
 }
 
 template <int PER>
+void launch_cells_small(nnp_model& m, const float* pos, int n, const LinkArgs& L, hipStream_t st) {
+  hipLaunchKernelGGL(k_cells_small<PER>, dim3(1), dim3(kScanThreads), 0, st, pos, n, m.d_idx, m.d_sigma, m.geo, L,
+                     m.S, m.d_key, m.d_bin_start, m.d_perm, m.d_spos, m.d_slot_atom, m.d_order, m.d_sbin,
+                     m.d_islot, m.d_pcount, m.d_status);
+}
+
+template <int PER>
 void launch_scan_scatter(nnp_model& m, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_scatter<PER>, dim3(blocks_for(n, kScanThreads)), dim3(kScanThreads), 0, st,
                      m.d_bin_count, m.d_bin_start, m.d_cmstart, m.S, m.geo.n_bins, m.d_key, m.d_rank, n, m.d_tmp);
@@ -981,6 +1085,16 @@ hipError_t launch_cells(nnp_model& m, const float* pos, int n, hipStream_t st) {
   const Geometry& g = m.geo;
   LinkArgs L{m.d_link_ml, m.d_link_mm, m.link_d, m.n_links_dev};
   int nb = m.S * g.n_bins;
+  if (n > 0 && g.periodic && n <= kSmallCells && nb <= kScanChunk) {
+    switch (scan_entries_per_thread(nb)) {
+      case 1: launch_cells_small<1>(m, pos, n, L, st); break;
+      case 2: launch_cells_small<2>(m, pos, n, L, st); break;
+      case 4: launch_cells_small<4>(m, pos, n, L, st); break;
+      case 8: launch_cells_small<8>(m, pos, n, L, st); break;
+      default: launch_cells_small<16>(m, pos, n, L, st); break;
+    }
+    return hipGetLastError();
+  }
   if (n > 0) {
     hipLaunchKernelGGL(k_stage, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, pos, n, m.d_idx,
                        m.d_sigma, m.d_sys, g, L, m.d_key, m.d_rank, m.d_stg, m.d_bin_count, m.d_status);
