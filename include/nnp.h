@@ -134,9 +134,12 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
  * Allocate the workspace for up to max_atoms atoms (all atoms of a call,
  * NNP or not), max_systems systems in one batched call, max_mm MM charges,
  * and per-atom neighbour-list capacities max_rad_nbr (within rc_rad) and
- * max_ang_nbr (within rc_ang); 0 selects the defaults 128 and 64.  May be
- * called again to grow or shrink; synchronises the device.  All device
- * allocation of the model happens here and in nnp_create.
+ * max_ang_nbr (within rc_ang); 0 selects the defaults 128 and 64.  For a
+ * model with extra_inputs, max_mm also sizes the MM channel's per-workgroup
+ * partial sums: 12 bytes per atom for every 256 charges, at most 512 such
+ * groups (6 KiB per atom).  May be called again to grow or shrink;
+ * synchronises the device.  All device allocation of the model happens here
+ * and in nnp_create.
  */
 nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int32_t max_mm,
                        int32_t max_rad_nbr, int32_t max_ang_nbr);
