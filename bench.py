@@ -123,7 +123,7 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
             return f"k_mlp_split8<{dims}, {1 if nv == 5 else 2}, {'true' if nv == 6 else 'false'}>"
         return f"k_mlp_reg<{dims}>" if nv == 0 else f"k_mlp_split<{dims}, {cols}>"
     if stage == "adjoint":
-        return ["k_desc_bwd<64>", "k_desc_bwd<32>"][v.get("adjoint", 0)]
+        return ["k_desc_bwd<64, false>", "k_desc_bwd<32, false>", "k_desc_bwd<64, true>"][v.get("adjoint", 0)]
     return {"gather": "k_force_gather", "energy": "k_force_gather", "mm": "k_mm_fwd",
             "mm_adjoint": "k_mm_bwd"}.get(stage)
 

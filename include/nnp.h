@@ -267,7 +267,8 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
  * or of 32 atoms with 16 for the smallest species, with four or eight
  * wavefronts;
  * descriptor forward: a wavefront, a 16-lane or an 8-lane row per atom; descriptor
- * adjoint: a wavefront or half a wavefront per atom; neighbour search: one
+ * adjoint: a wavefront or half a wavefront per atom, and a wide-load form of
+ * its reverse-slot search; neighbour search: one
  * wavefront per atom, or several per cell sharing its centre atoms).
  * nnp_autotune reruns the
  * stages after the cell list `reps` times (1..256) per candidate on the
@@ -305,7 +306,9 @@ typedef enum {
  *     atoms (more even workgroups for small systems); 5 / 6 / 7 as 1 / 4 / 2
  *     with eight wavefronts per workgroup instead of four (shorter chains
  *     per tile, for systems with few tiles or wide networks);
- *   descriptor adjoint: 0 one wavefront per atom; 1 half a wavefront per atom.
+ *   descriptor adjoint: 0 one wavefront per atom; 1 half a wavefront per atom;
+ *     2 as 0, with the centre's place in each neighbour's list counted with
+ *     wide loads instead of a binary search (for lists far beyond the caches).
  * All variants compute the same quantities (integer stages bit-identically,
  * floating point to rounding).
  * Drops the cached graph.  NNP_EINVAL for an unknown stage or variant.

@@ -480,8 +480,9 @@ __host__ __device__ __forceinline__ size_t bwd_lds_per_atom(int max_rad, int max
 
 // LANES lanes per atom: 64 (one atom per wavefront) or 32 (two atoms per
 // wavefront, so that the ~153 triplets of an atom in water fill the lanes
-// with less rounding).
-template <int LANES>
+// with less rounding).  WIDE: the centre's place in each neighbour's list is
+// counted with wide loads instead of a binary search (step 5).
+template <int LANES, bool WIDE>
 __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geometry geo) {
   constexpr int APW = 64 / LANES;   // atoms per wavefront
   extern __shared__ double smem_d[];
@@ -654,18 +655,52 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
     }
   }
   __syncthreads();
-  // 5. each neighbour's total goes to the centre's slot in the neighbour's list
+  // 5. each neighbour's total goes to the centre's slot in the neighbour's list:
+  // in j's species segment [lo, hi) (sorted by slot) the centre sits after the
+  // entries below i.  A binary search finds it with one dependent load per
+  // halving.  The WIDE form counts the entries below i 32 at a time from
+  // eight independent aligned 16-byte loads: one or two round trips instead
+  // of about six, for four times the bytes.  That wins when the lists are
+  // far beyond the caches (261k atoms: 687 -> 642 us) and loses while they
+  // are cache-resident (12k atoms: 34 -> 42 us), so it is a tuned variant.
   const int si = __float_as_int(pi.w);
+  const bool wide = WIDE && (a.max_rad & 3) == 0;   // rows start on 16-byte boundaries
   for (int t = lane; t < nr; t += LANES) {
     const int j = rrow[t];
     const int* jrow = a.rad + (int64_t)j * a.max_rad;
-    int lo = a.rad_off[(int64_t)j * S1 + si], hi = a.rad_off[(int64_t)j * S1 + si + 1] - 1;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (jrow[mid] < i) lo = mid + 1; else hi = mid;
+    const int lo = a.rad_off[(int64_t)j * S1 + si], hi = a.rad_off[(int64_t)j * S1 + si + 1];
+    int pos = -1;
+    if (wide) {
+      int below = 0;
+      bool hit = false;
+      for (int e0 = lo & ~3; e0 < hi; e0 += 32) {
+        int4 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)   // a load starting before hi stays inside the row (max_rad % 4 == 0)
+          q[u] = e0 + 4 * u < hi ? reinterpret_cast<const int4*>(jrow + e0)[u] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int e = e0 + 4 * u + c;
+            const bool in = e >= lo && e < hi;
+            below += (in && v[c] < i) ? 1 : 0;
+            hit = hit || (in && v[c] == i);
+          }
+        }
+      }
+      if (hit) pos = lo + below;
+    } else {
+      int l = lo, h = hi - 1;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (jrow[mid] < i) l = mid + 1; else h = mid;
+      }
+      if (l <= h && jrow[l] == i) pos = l;
     }
-    if (lo <= hi && jrow[lo] == i)
-      a.contrib[(int64_t)j * a.max_rad + lo] = make_float3((float)-sx[t], (float)-sy[t], (float)-sz[t]);
+    if (pos >= 0)
+      a.contrib[(int64_t)j * a.max_rad + pos] = make_float3((float)-sx[t], (float)-sy[t], (float)-sz[t]);
   }
   // 6. the centre's own total
   double dx = part_sum_d<LANES>((double)fx), dy = part_sum_d<LANES>((double)fy), dz = part_sum_d<LANES>((double)fz);
@@ -851,7 +886,8 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
 }
 
 // Adjoint variants: 0 = one wavefront per atom (default; measured faster on
-// water boxes), 1 = half a wavefront per atom.
+// water boxes), 1 = half a wavefront per atom, 2 = variant 0 with the wide
+// reverse-slot count (for lists far beyond the caches).
 int adjoint_variant(const nnp_model& m, int n) {
   const int v = stage_variant(m, kTuneAdjoint, n);
   return v >= 0 ? v : 0;
@@ -874,10 +910,13 @@ hipError_t launch_descriptor_bwd(nnp_model& m, int n, hipStream_t st) {
   a.contrib = m.d_contrib;
   a.self = m.d_self;
   const size_t per_atom = bwd_lds_per_atom(m.max_rad, m.max_ang, m.stride);
-  if (adjoint_variant(m, n) == 1) {
-    hipLaunchKernelGGL(k_desc_bwd<32>, dim3((n + 1) / 2), dim3(64), 2 * per_atom, st, a, m.dp, m.geo);
+  const int v = adjoint_variant(m, n);
+  if (v == 1) {
+    hipLaunchKernelGGL((k_desc_bwd<32, false>), dim3((n + 1) / 2), dim3(64), 2 * per_atom, st, a, m.dp, m.geo);
+  } else if (v == 2) {
+    hipLaunchKernelGGL((k_desc_bwd<64, true>), dim3(n), dim3(64), per_atom, st, a, m.dp, m.geo);
   } else {
-    hipLaunchKernelGGL(k_desc_bwd<64>, dim3(n), dim3(64), per_atom, st, a, m.dp, m.geo);
+    hipLaunchKernelGGL((k_desc_bwd<64, false>), dim3(n), dim3(64), per_atom, st, a, m.dp, m.geo);
   }
   return hipGetLastError();
 }

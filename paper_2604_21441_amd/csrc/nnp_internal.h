@@ -261,7 +261,7 @@ int adjoint_variant(const nnp_model& m, int n);
 // Variant of a tuned stage: the candidate being timed, else the pinned one,
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
-constexpr int kStageVariants[kTuneStages] = {4, 3, 8, 2};
+constexpr int kStageVariants[kTuneStages] = {4, 3, 8, 3};
 int size_bucket(int n);
 
 // error helpers (api.cpp)

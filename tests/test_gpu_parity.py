@@ -292,7 +292,7 @@ def test_autotune_keeps_results(P, w_water):
         E0, F0 = E0.clone(), F0.clone()
         chosen = m.autotune(3)
         assert 0 <= chosen["network"] < 8 and chosen["neighbours"] in (0, 1, 2, 3)
-        assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1)
+        assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1, 2)
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
         assert m.status() == 0
@@ -313,7 +313,7 @@ VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours",
             ("network", 7, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
             ("network", 3, "bf16"), ("network", 4, "bf16"), ("network", 5, "bf16"), ("network", 6, "bf16"),
             ("network", 7, "bf16"), ("adjoint", 0, "fp32"),
-            ("adjoint", 1, "fp32")]
+            ("adjoint", 1, "fp32"), ("adjoint", 2, "fp32")]
 
 
 @pytest.mark.parametrize("stage,variant,prec", VARIANTS)
@@ -337,7 +337,7 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    nvar = {"network": 8, "neighbours": 4, "descriptor": 3, "adjoint": 2}[stage]
+    nvar = {"network": 8, "neighbours": 4, "descriptor": 3, "adjoint": 3}[stage]
     for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
@@ -393,6 +393,39 @@ def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
         if ref is None:
             ref = F
         assert np.array_equal(F, ref), f"network variant {v}"
+
+
+def test_adjoint_wide_reverse_search_bit_identical(P, w_water, w_hcno, boxes):
+    """Adjoint variant 2 finds each centre's place in its neighbours' lists by
+    counting with wide loads instead of a binary search; the places, hence
+    every force, are the same bit for bit.  Covered: water boxes of two sizes,
+    open H/C/N/O molecules (uneven species segments), and a radial capacity
+    that is not a multiple of four (rows not 16-byte aligned: the variant
+    falls back to the binary search)."""
+    cases = [("c1", None), ("c2", None), ("c2", 126)]
+    for name, cap in cases:
+        pos, Z, box = boxes[name]
+        F = {}
+        for v in (0, 2):
+            m = P.NNPModel(WATER, weights=sy.flat_weights(w_water))
+            if cap is not None:
+                m.reserve(len(Z), max_rad_nbr=cap)
+            m.set_variant("adjoint", v)
+            F[v] = _run(m, pos, Z, box)[1]
+            m.close()
+        assert np.array_equal(F[0], F[2]), (name, cap)
+    pos, Z, off = sy.walk_batch(24, seed=9)
+    d = torch.from_numpy(pos).cuda()
+    F = {}
+    for v in (0, 2):
+        m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno))
+        m.set_variant("adjoint", v)
+        E, Fv = m.compute_batch(d, Z, off)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        F[v] = Fv.cpu().numpy()
+        m.close()
+    assert np.array_equal(F[0], F[2])
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
