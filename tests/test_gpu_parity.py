@@ -618,6 +618,41 @@ def test_mm_charge_channel(P):
     assert np.abs(F.sum(0) + Fmm.sum(0)).max() < 1e-4
 
 
+def test_mm_channel_charge_counts(P):
+    """The MM channel at the edges of its grid: more charges than 512
+    workgroups of 256 lanes cover (each lane then takes several charges), and
+    a model with the MM input called with no charges (phi = 0: compared with
+    the oracle given zero charges)."""
+    sysd = sy.solute_in_water(seed=0)
+    w = sy.model_weights(HCNO_MM, seed=3)
+    L = float(sysd["box"][0])
+    rng = np.random.default_rng(11)
+    n_mm = 140_000                                  # > 512 * 256
+    y = rng.uniform(0.0, L, size=(2 * n_mm, 3))
+    d = y[:, None, :] - sysd["pos"].astype(np.float64)[None, :, :]
+    d -= L * np.rint(d / L)
+    far = np.min(np.einsum("mak,mak->ma", d, d), axis=1) > 4.0   # no charge within 2 A of the solute
+    y = np.ascontiguousarray(y[far][:n_mm].astype(np.float32))
+    q = rng.uniform(-0.5, 0.5, size=n_mm)
+    q = (q - q.mean()).astype(np.float32)
+    ref = orc.evaluate(sysd["pos"], sysd["Z"], HCNO_MM, w, box=sysd["box"], mm_pos=y, mm_q=q)
+    m = P.NNPModel(HCNO_MM, weights=sy.flat_weights(w), precision="fp32")
+    E, F, Fmm = _run(m, sysd["pos"], sysd["Z"], sysd["box"], mm_pos=torch.from_numpy(y).cuda(),
+                     mm_q=torch.from_numpy(q).cuda())
+    n = len(sysd["Z"])
+    assert abs(E[0] - ref["E"]) / n < 1e-6
+    assert rel_rmse(np.concatenate([F, Fmm]), np.concatenate([ref["F"], ref["F_mm"]])) < 1e-5
+    # no charges
+    zq = np.zeros(4, dtype=np.float32)
+    ref0 = orc.evaluate(sysd["pos"], sysd["Z"], HCNO_MM, w, box=sysd["box"], mm_pos=y[:4], mm_q=zq)
+    e0 = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    E0, F0, _ = _run(m, sysd["pos"], sysd["Z"], sysd["box"], mm_pos=e0,
+                     mm_q=torch.empty((0,), dtype=torch.float32, device="cuda"))
+    assert abs(E0[0] - ref0["E"]) / n < 1e-6
+    assert rel_rmse(F0, ref0["F"]) < 1e-5
+    m.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_predicted_charge_embedding(P, prec):
     """Electrostatic embedding with charges from the network (a second output
