@@ -40,7 +40,8 @@ import torch
 __all__ = [
     "species_index", "pair_class_table", "neighbour_pairs", "neighbour_pairs_bruteforce",
     "cutoff", "celu", "descriptors", "mlp_outputs", "mlp_energies", "mlp_input_grad", "evaluate",
-    "evaluate_batch", "cell_list_fp32", "neighbours_fp32", "mm_potential", "link_atom_positions",
+    "evaluate_batch", "cell_list_fp32", "neighbours_fp32", "neighbours_fp32_kdtree", "mm_potential",
+    "link_atom_positions",
     "me_coupling",
 ]
 
@@ -153,8 +154,12 @@ def cutoff(r, rc):
 
 
 def celu(u, alpha):
-    """CELU_alpha(u) = max(0, u) + min(0, alpha (exp(u/alpha) - 1))."""
-    return torch.clamp(u, min=0.0) + torch.clamp(alpha * (torch.exp(u / alpha) - 1.0), max=0.0)
+    """CELU_alpha(u) = max(0, u) + min(0, alpha (exp(u/alpha) - 1)).
+
+    The second term vanishes for u >= 0, so its exponent is taken at min(u, 0):
+    the same function, without exp overflowing (and its gradient turning NaN)
+    for large positive u."""
+    return torch.clamp(u, min=0.0) + torch.clamp(alpha * torch.expm1(torch.clamp(u, max=0.0) / alpha), max=0.0)
 
 
 def _min_image_t(d, box_t):
@@ -350,7 +355,8 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
                energies are summed (E and the gradient then cover only those);
                used to get exact forces on sampled atoms of very large systems.
     links    : optional (ml_idx, mm_idx, d, Z_link): link atoms placed by eq. 4
-               on the bonds ml -> mm (ml in the index group, mm outside); they
+               on the bonds ml -> mm (ml in the index group, mm outside; the
+               bond vector under the minimum image when ``box`` is given); they
                are NNP atoms appended after the index group, and their forces
                reach the ML and MM atoms through the chain rule (autograd
                through the link positions).
@@ -370,7 +376,7 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
     def nnp_positions():
         p = full[torch.tensor(idx)]
         if links is not None and ml.size:
-            rl = link_atom_positions(full[torch.tensor(ml)], full[torch.tensor(mmi)], float(d_link))
+            rl = link_atom_positions(full[torch.tensor(ml)], full[torch.tensor(mmi)], float(d_link), box)
             p = torch.cat([p, rl])
         return p
 
@@ -418,14 +424,22 @@ def evaluate(pos, Z, cfg, weights, box=None, nnp_idx=None, mm_pos=None, mm_q=Non
     return out
 
 
-def evaluate_batch(pos, Z, offsets, cfg, weights, forces=True):
-    """Independent non-periodic systems packed back to back: per-system E and all forces."""
+def evaluate_batch(pos, Z, offsets, cfg, weights, forces=True, boxes=None):
+    """Independent systems packed back to back: per-system E and all forces.
+
+    boxes: None (every system open), or [n_sys][3] orthorhombic box lengths per
+    system, a row of zeros (or NaN) marking an open system."""
     offsets = np.asarray(offsets)
     E = np.zeros(offsets.size - 1)
     F = np.zeros((pos.shape[0], 3))
     for m in range(offsets.size - 1):
         a, b = int(offsets[m]), int(offsets[m + 1])
-        r = evaluate(pos[a:b], Z[a:b], cfg, weights, box=None, forces=forces)
+        box = None
+        if boxes is not None:
+            row = np.asarray(boxes[m], np.float64)
+            if np.all(np.isfinite(row)) and np.all(row > 0):
+                box = row
+        r = evaluate(pos[a:b], Z[a:b], cfg, weights, box=box, forces=forces)
         E[m] = r["E"]
         if forces:
             F[a:b] = r["F"]
@@ -435,11 +449,18 @@ def evaluate_batch(pos, Z, offsets, cfg, weights, forces=True):
 # --------------------------------------------------------------------------
 # Link atoms (eq. 4): r_L = r_ML + d (r_MM - r_ML) / |r_MM - r_ML|.
 # --------------------------------------------------------------------------
-def link_atom_positions(r_ml, r_mm, d=1.0):
-    """Positions of link atoms placed at distance d from the ML atom along the ML-MM bond."""
+def link_atom_positions(r_ml, r_mm, d=1.0, box=None):
+    """Positions of link atoms placed at distance d from the ML atom along the ML-MM bond.
+
+    In a periodic box the bond is the shortest one between the two atoms: u is
+    taken under the minimum image, u - L round(u / L) per component (a bond is
+    far shorter than half a box length, so this is the bonded copy of the MM
+    atom whichever images the caller's coordinates hold)."""
     r_ml = torch.as_tensor(r_ml, dtype=torch.float64)
     r_mm = torch.as_tensor(r_mm, dtype=torch.float64)
     u = r_mm - r_ml
+    if box is not None:
+        u = _min_image_t(u, torch.tensor(np.asarray(box, np.float64)))
     return r_ml + d * u / torch.sqrt(torch.sum(u * u, dim=-1, keepdim=True))
 
 
@@ -552,3 +573,49 @@ def neighbours_fp32(pos32, rc32, box32=None):
     J = np.concatenate(J) if J else np.zeros(0, np.int64)
     o = np.lexsort((J, I))
     return I[o].astype(np.int64), J[o].astype(np.int64)
+
+
+def _fp32_pair_r2(pos32, I, J, box32):
+    """r2 of the directed pairs (I, J) by the float32 operations of ``neighbours_fp32``."""
+    d = (pos32[J] - pos32[I]).astype(_F32)
+    if box32 is not None:
+        inv = (_F32(1.0) / box32).astype(_F32)
+        sh = np.rint((d * inv).astype(_F32)).astype(_F32)
+        d = (d - (sh * box32).astype(_F32)).astype(_F32)
+    sq = (d * d).astype(_F32)
+    return ((sq[:, 0] + sq[:, 1]).astype(_F32) + sq[:, 2]).astype(_F32)
+
+
+def neighbours_fp32_kdtree(pos32, rc32, box32=None, margin=0.01):
+    """The pair set of ``neighbours_fp32`` for systems too large for its O(N^2) scan.
+
+    Candidates are the pairs a k-d tree (scipy cKDTree, float64 geometry of the
+    same FP32 coordinates, periodic with ``boxsize`` when a box is given) finds
+    within rc + margin; the float32 predicate of ``neighbours_fp32`` then decides
+    each candidate in both directions.  The margin (0.01 A) is far above the
+    float32 rounding of a displacement, so no pair the predicate accepts is
+    missed.  Returns (i, j) sorted by i then j.
+    """
+    from scipy.spatial import cKDTree
+    pos32 = np.asarray(pos32, dtype=_F32)
+    n = pos32.shape[0]
+    if n < 2:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    p64 = pos32.astype(np.float64)
+    if box32 is not None:
+        box32 = np.asarray(box32, dtype=_F32)
+        L = box32.astype(np.float64)
+        w = p64 - L * np.floor(p64 / L)
+        w = np.where(w >= L, w - L, w)
+        w = np.where(w < 0, 0.0, w)
+        tree = cKDTree(w, boxsize=L)
+    else:
+        tree = cKDTree(p64)
+    pr = tree.query_pairs(r=float(rc32) + margin, output_type="ndarray").astype(np.int64)
+    I = np.concatenate([pr[:, 0], pr[:, 1]])
+    J = np.concatenate([pr[:, 1], pr[:, 0]])
+    rc2 = _F32(_F32(rc32) * _F32(rc32))
+    keep = _fp32_pair_r2(pos32, I, J, box32) < rc2
+    I, J = I[keep], J[keep]
+    o = np.lexsort((J, I))
+    return I[o], J[o]

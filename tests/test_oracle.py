@@ -692,3 +692,180 @@ def test_me_coupling_third_law_and_fd():
             Em = orc.me_coupling(*args_m, sy.KE_COULOMB, box=L, cutoff=8.5, forces=False)[0]
             fd = -(Ep - Em) / (2 * h)
             assert abs(fd - F[idx, k]) < 1e-6 * max(1.0, abs(F[idx, k]))
+
+
+# ------------------------------------------- link atoms across a periodic boundary
+def _images_nearest(r_ml, r_mm, L):
+    """Brute force: the periodic copy r_mm + L k (k in {-4..4}^3) nearest to r_ml."""
+    ks = np.array([(a, b, c) for a in range(-4, 5) for b in range(-4, 5) for c in range(-4, 5)], np.float64)
+    cands = r_mm[None, :] + ks * L[None, :]
+    return cands[np.argmin(np.linalg.norm(cands - r_ml[None, :], axis=1))]
+
+
+def test_link_atom_minimum_image_brute_force():
+    """With a box, the link atom lies on the bond to the nearest periodic copy of the
+    MM atom, whatever image the caller's coordinates hold (nearest copy found by
+    enumerating images, not by rounding)."""
+    rng = np.random.default_rng(11)
+    L = np.array([21.0, 23.5, 19.25])
+    for _ in range(50):
+        r_ml = rng.uniform(0, 1, 3) * L
+        bond = rng.normal(size=3)
+        bond *= rng.uniform(1.0, 1.6) / np.linalg.norm(bond)
+        r_mm = r_ml + bond + L * rng.integers(-3, 4, size=3)       # any image
+        near = _images_nearest(r_ml, r_mm, L)
+        expect = r_ml + 1.0 * (near - r_ml) / np.linalg.norm(near - r_ml)
+        got = orc.link_atom_positions(r_ml[None], r_mm[None], 1.0, box=L).numpy()[0]
+        np.testing.assert_allclose(got, expect, atol=1e-12)
+        assert abs(np.linalg.norm(got - r_ml) - 1.0) < 1e-12
+
+
+def _cut_chain(pos, idx, n_all, cutoff=1.6):
+    d = np.linalg.norm(pos[:, None] - pos[None], axis=-1)
+    ml, mm = [], []
+    for a in idx:
+        for b in range(n_all):
+            if b not in set(idx) and d[a, b] < cutoff:
+                ml.append(a)
+                mm.append(b)
+    return np.array(ml), np.array(mm)
+
+
+def test_link_atoms_periodic_boundary_translation(w_hcno):
+    """A periodic ML subsystem with link atoms: translating every atom so that a cut
+    bond straddles the box face, then wrapping each atom into [0, L), leaves E and
+    every force unchanged.  (A link placed along the raw, unwrapped bond vector
+    would land about one box length away and change E.)"""
+    rng = np.random.Generator(np.random.PCG64(21))
+    pos, Z = sy.walk_molecule(30, rng)
+    pos = pos.astype(np.float64)
+    L = np.array([44.0, 44.0, 44.0])
+    idx = np.arange(18)
+    ml, mm = _cut_chain(pos, idx, 30)
+    assert ml.size
+    links = (ml, mm, 1.0, 1)
+    ref = orc.evaluate(pos, Z, HCNO, w_hcno, box=L, nnp_idx=idx, links=links)
+    # put the first cut bond's midpoint on the x = 0 face, then wrap every atom
+    mid = 0.5 * (pos[ml[0]] + pos[mm[0]])
+    shift = np.array([-mid[0], 3.7 - mid[1], 5.1 - mid[2]])
+    moved = pos + shift
+    wrapped = moved - L * np.floor(moved / L)
+    assert abs(wrapped[ml[0], 0] - wrapped[mm[0], 0]) > L[0] / 2, "the cut bond must straddle the face"
+    got = orc.evaluate(wrapped, Z, HCNO, w_hcno, box=L, nnp_idx=idx, links=links)
+    assert abs(got["E"] - ref["E"]) < 1e-10 * max(1.0, abs(ref["E"]))
+    np.testing.assert_allclose(got["F"], ref["F"], atol=1e-9)
+
+
+def test_link_atoms_straddling_bond_fd(w_hcno):
+    """Central differences of E on the ML and MM atoms of a cut bond that crosses
+    the periodic boundary (wrapped coordinates) match the oracle's forces."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    pos, Z = sy.walk_molecule(30, rng)
+    pos = pos.astype(np.float64)
+    L = np.array([44.0, 44.0, 44.0])
+    idx = np.arange(18)
+    ml, mm = _cut_chain(pos, idx, 30)
+    mid = 0.5 * (pos[ml[0]] + pos[mm[0]])
+    moved = pos + np.array([-mid[0], 0.0, 0.0])
+    pos = moved - L * np.floor(moved / L)
+    links = (ml, mm, 1.0, 1)
+    ref = orc.evaluate(pos, Z, HCNO, w_hcno, box=L, nnp_idx=idx, links=links)
+    h = 1e-4
+    for a in (ml[0], mm[0]):
+        for k in range(3):
+            p1 = pos.copy(); p1[a, k] += h
+            p2 = pos.copy(); p2[a, k] -= h
+            e1 = orc.evaluate(p1, Z, HCNO, w_hcno, box=L, nnp_idx=idx, links=links, forces=False)["E"]
+            e2 = orc.evaluate(p2, Z, HCNO, w_hcno, box=L, nnp_idx=idx, links=links, forces=False)["E"]
+            fd = -(e1 - e2) / (2 * h)
+            assert abs(fd - ref["F"][a, k]) < 2e-7 * max(1.0, abs(ref["F"][a, k])), (a, k, fd, ref["F"][a, k])
+
+
+# ---------------------------------------------------------- network input gradient
+def test_mlp_input_grad_central_differences(w_water, w_hcno):
+    """d e_i / d x_i of ``mlp_input_grad`` against central differences of the atomic
+    energies in float64, for random descriptor rows of both networks."""
+    rng = np.random.default_rng(8)
+    for cfg, w in ((WATER, w_water[0]), (HCNO, w_hcno[0])):
+        D = cfg["widths"][0]
+        S = len(cfg["species"])
+        x = rng.uniform(0.0, 1.5, size=(2 * S, D))
+        sig = np.arange(2 * S) % S
+        e, g = orc.mlp_input_grad(x, sig, w, cfg["celu_alpha"])
+        h = 1e-5
+        cols = rng.choice(D, 12, replace=False)
+        for r in range(x.shape[0]):
+            for c in cols:
+                xp = x.copy(); xp[r, c] += h
+                xm = x.copy(); xm[r, c] -= h
+                ep = orc.mlp_energies(torch.tensor(xp), sig, w, cfg["celu_alpha"]).numpy()[r]
+                em = orc.mlp_energies(torch.tensor(xm), sig, w, cfg["celu_alpha"]).numpy()[r]
+                fd = (ep - em) / (2 * h)
+                assert abs(fd - g[r, c]) < 1e-7 * max(1.0, abs(g[r, c])), (r, c, fd, g[r, c])
+
+
+def test_mlp_input_grad_linear_regime_closed_form():
+    """With every hidden pre-activation positive, CELU is the identity and the network
+    is the affine map W4 W3 W2 W1 x + const, so d e / d x = (W4 W3 W2 W1)[0]: a
+    product of the weight matrices by numpy matmul, independent of the autograd path."""
+    rng = np.random.default_rng(2)
+    widths = [128, 160, 128, 96, 1]
+    layers = []
+    for l in range(4):
+        W = np.abs(rng.normal(0, 0.05, size=(widths[l + 1], widths[l])))   # non-negative
+        b = np.full(widths[l + 1], 0.5)
+        layers.append((W, b))
+    x = rng.uniform(0.0, 1.0, size=(3, 128))                                 # non-negative inputs
+    e, g = orc.mlp_input_grad(x, np.zeros(3, np.int64), [layers], 0.1)
+    J = layers[3][0] @ layers[2][0] @ layers[1][0] @ layers[0][0]
+    np.testing.assert_allclose(g, np.repeat(J, 3, axis=0), rtol=1e-12, atol=1e-14)
+    h = x
+    for W, b in layers:
+        h = h @ W.T + b
+    np.testing.assert_allclose(e, h[:, 0], rtol=1e-12)
+
+
+# ------------------------------------------------- k-d tree FP32 neighbour oracle
+@pytest.mark.parametrize("case", ["c1", "shifted", "open"])
+def test_kdtree_fp32_pairs_equal_bruteforce(case):
+    """``neighbours_fp32_kdtree`` (used for boxes too large for the O(N^2) scan) returns
+    exactly the pair set of the brute-force float32 definition, for both cutoffs."""
+    if case == "c1":
+        pos, Z, box = sy.water_box(64, 12.42, seed=0)
+    elif case == "shifted":
+        pos, Z, box = sy.water_box(1000, 31.07, seed=5)
+        k = np.random.default_rng(3).integers(-3, 4, size=pos.shape)
+        pos = (pos + k * np.asarray(box)).astype(np.float32)
+    else:
+        pos, Z, _ = sy.walk_batch(6, seed=2)
+        box = None
+    for rc in (5.2, 3.5):
+        I, J = orc.neighbours_fp32(pos, rc, box)
+        I2, J2 = orc.neighbours_fp32_kdtree(pos, rc, box)
+        assert np.array_equal(I, I2) and np.array_equal(J, J2)
+
+
+def test_kdtree_fp32_pairs_equal_bruteforce_12288():
+    """The same equality on the 4,096-water (12,288-atom) box at the radial cutoff."""
+    pos, Z, box = sy.water_box(4096, 49.7, seed=0)
+    I, J = orc.neighbours_fp32(pos, 5.2, box)
+    I2, J2 = orc.neighbours_fp32_kdtree(pos, 5.2, box)
+    assert I.size > 700000
+    assert np.array_equal(I, I2) and np.array_equal(J, J2)
+
+
+def test_periodic_batch_equals_separate_systems(w_water):
+    """evaluate_batch with per-system boxes: each system as its own periodic call; a
+    zero box row is an open system."""
+    a = sy.water_box(64, 12.42, seed=0)
+    b = sy.water_box(80, 13.38, seed=1)
+    pos = np.concatenate([a[0], b[0]])
+    Z = np.concatenate([a[1], b[1]])
+    off = np.array([0, 192, 432])
+    boxes = np.array([a[2], [0.0, 0.0, 0.0]], np.float32)
+    E, F = orc.evaluate_batch(pos, Z, off, WATER, w_water, boxes=boxes)
+    ra = orc.evaluate(a[0], a[1], WATER, w_water, box=a[2])
+    rb = orc.evaluate(b[0], b[1], WATER, w_water, box=None)
+    assert E[0] == ra["E"] and E[1] == rb["E"]
+    np.testing.assert_array_equal(F[:192], ra["F"])
+    np.testing.assert_array_equal(F[192:], rb["F"])
