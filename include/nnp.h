@@ -207,6 +207,30 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
                              double* forces, hipStream_t stream);
 
 /*
+ * nnp_compute without any allocation, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation).  Computes what nnp_compute computes for
+ * one system whose n_atoms atoms are all NNP atoms (index group = all, no MM
+ * charges, no link atoms), overwriting energy [1] and forces [n_atoms][3]
+ * (FP64, device).  pos [n_atoms][3] FP32 device, Z_host [n_atoms] host,
+ * box_host [3] host or NULL (open system), as for nnp_compute.
+ * The per-call workspace is carved out of a static device array of 32 MiB
+ * that the library holds on each device it runs on until the process ends;
+ * nnp_reserve is not needed and the reserved workspace, the captured graph
+ * and the topology cache of nnp_compute are left untouched (nnp_read_buffer
+ * keeps reporting nnp_compute's last call).  Kernels are launched directly
+ * on `stream` (no graph).  The array holds the workspace of up to about 8,900
+ * atoms of the two-species model or 5,700 of the four-species one, at the
+ * default neighbour capacities (128 radial, 64 angular); a larger call returns
+ * NNP_ECAPACITY before any work is queued.  All calls on one device share its
+ * array: calls that overlap on a device (other streams, other threads) race
+ * and must be serialised by the caller.  NNP_EINVAL for a model with the MM
+ * channel, NNP_ESTATE while link atoms are set; other errors as nnp_compute.
+ */
+nnp_status nnp_compute_noalloc(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
+                               const float* box_host, double* energy, double* forces, hipStream_t stream);
+
+/*
  * Link atoms for bonds cut by the index group (Methods, "The nnpot Interface",
  * eq. 4).  For each of the n_links cut bonds (ml_idx_host[l] inside the index
  * group, mm_idx_host[l] outside it; atom indices of the system passed to

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnnp.so")
 
-SOURCES = ["api.cpp", "weights.cpp", "cells.hip", "descriptor.hip", "mlp.hip", "mm.hip", "embed.hip"]
+SOURCES = ["api.cpp", "weights.cpp", "cells.hip", "descriptor.hip", "mlp.hip", "mm.hip", "embed.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 COMMON = [

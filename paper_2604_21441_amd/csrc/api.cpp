@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "nnp_internal.h"
@@ -37,6 +38,69 @@ int stage_variant(const nnp_model& m, int stage, int n) {
   if (m.force_variant[stage] >= 0) return m.force_variant[stage];
   if (m.pinned[stage] >= 0) return m.pinned[stage];
   return tuned_choice(m, stage, n);
+}
+
+Workspace workspace_caps(const nnp_model& m, int max_atoms, int max_systems, int max_mm, int max_rad,
+                         int max_ang) {
+  Workspace w;
+  w.max_atoms = max_atoms;
+  w.max_sys = max_systems;
+  w.max_mm = max_mm;
+  w.max_rad = max_rad;
+  w.max_ang = max_ang;
+  const int cells_cap = max_atoms > 64 ? max_atoms : 64;
+  const int per_species_bins = cells_cap > max_systems ? cells_cap : max_systems;
+  w.max_bins = m.S * per_species_bins;
+  w.max_part = max_atoms / kTileAtoms + 2 * kMaxSpecies + 8;
+  return w;
+}
+
+// Every array of the workspace at its own 256-byte aligned offset from `base`
+// (a null base only measures).  The pointers are written into w.
+size_t carve_workspace(const nnp_model& m, Workspace& w, char* base) {
+  size_t off = 0;
+  auto take = [&](auto*& p, size_t count) {
+    using T = std::remove_reference_t<decltype(*p)>;
+    off = (off + 255) & ~size_t(255);
+    p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (count ? count : 1) * sizeof(T);
+  };
+  const size_t n = (size_t)w.max_atoms;
+  take(w.d_idx, n);
+  take(w.d_sigma, n);
+  take(w.d_sys, n);
+  take(w.d_sys_off, (size_t)w.max_sys + 2);
+  take(w.d_key, n);
+  take(w.d_perm, n);
+  take(w.d_tmp, n);
+  take(w.d_rank, n);
+  take(w.d_slot_atom, n);
+  take(w.d_sbin, n);
+  take(w.d_loc, n);
+  take(w.d_islot, n);
+  take(w.d_pcount, n);
+  take(w.d_spos, n);
+  take(w.d_stg, n);
+  take(w.d_bin_count, (size_t)w.max_bins);
+  take(w.d_bin_start, (size_t)w.max_bins + 1);
+  take(w.d_cmstart, (size_t)w.max_bins);
+  take(w.d_order, n);
+  take(w.d_nbr_rad, n * w.max_rad);
+  take(w.d_nbr_ang, n * w.max_ang);
+  take(w.d_rad_off, n * (m.S + 1));
+  take(w.d_ang_off, n * (m.S + 1));
+  take(w.d_angpos, n * w.max_ang);
+  take(w.d_contrib, n * w.max_rad);
+  take(w.d_self, 3 * n);
+  take(w.d_part, (size_t)w.max_part);
+  take(w.d_x, n * m.stride);
+  take(w.d_g, n * m.stride);
+  take(w.d_e, n);
+  w.d_mm_part = nullptr;
+  if (m.extra && w.max_mm > 0) take(w.d_mm_part, mm_partial_floats(w.max_atoms, w.max_mm));
+  w.d_q = nullptr;
+  if (m.charges) take(w.d_q, n);
+  return (off + 255) & ~size_t(255);
 }
 
 namespace {
@@ -121,11 +185,9 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
 }
 
 void free_workspace(nnp_model* m) {
-  dfree(m->d_idx); dfree(m->d_sigma); dfree(m->d_sys); dfree(m->d_sys_off); dfree(m->d_key); dfree(m->d_bin_count);
-  dfree(m->d_bin_start); dfree(m->d_cmstart); dfree(m->d_order); dfree(m->d_perm); dfree(m->d_tmp); dfree(m->d_rank); dfree(m->d_spos); dfree(m->d_stg);
-  dfree(m->d_slot_atom); dfree(m->d_sbin); dfree(m->d_loc); dfree(m->d_islot); dfree(m->d_pcount); dfree(m->d_nbr_rad); dfree(m->d_nbr_ang); dfree(m->d_rad_off);
-  dfree(m->d_ang_off); dfree(m->d_angpos); dfree(m->d_contrib); dfree(m->d_self); dfree(m->d_part);
-  dfree(m->d_x); dfree(m->d_g); dfree(m->d_e); dfree(m->d_mm_part); dfree(m->d_q);
+  if (m->d_ws_base) (void)hipFree(m->d_ws_base);
+  m->d_ws_base = nullptr;
+  static_cast<Workspace&>(*m) = Workspace{};
   if (m->h_stage) (void)hipHostFree(m->h_stage);
   m->h_stage = nullptr;
   m->reserved = false;
@@ -331,6 +393,13 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
     nnp_destroy(m);
     return hip_error(e, "nnp_create");
   }
+  {
+    nnp_status st = noalloc_scratch_setup(m->device);
+    if (st != NNP_OK) {
+      nnp_destroy(m);
+      return st;
+    }
+  }
   load_tuning(m);
   *out = m;
   return NNP_OK;
@@ -345,55 +414,21 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
     return set_error(NNP_EINVAL, "neighbour capacities are limited to 1024 (radial) and 256 (angular)");
   HIP_TRY(hipDeviceSynchronize(), "nnp_reserve");
   free_workspace(m);
-  m->max_atoms = max_atoms;
-  m->max_sys = max_systems;
-  m->max_mm = max_mm;
-  m->max_rad = max_rad_nbr ? max_rad_nbr : 128;
-  m->max_ang = max_ang_nbr ? max_ang_nbr : 64;
-  int cells_cap = max_atoms > 64 ? max_atoms : 64;
-  int per_species_bins = cells_cap > max_systems ? cells_cap : max_systems;
-  m->max_bins = m->S * per_species_bins;
-  const size_t n = (size_t)max_atoms;
-  hipError_t e = hipSuccess;
-  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-  chk(dalloc(&m->d_idx, n));
-  chk(dalloc(&m->d_sigma, n));
-  chk(dalloc(&m->d_sys, n));
-  chk(dalloc(&m->d_sys_off, (size_t)max_systems + 2));
-  chk(dalloc(&m->d_key, n));
-  chk(dalloc(&m->d_perm, n));
-  chk(dalloc(&m->d_tmp, n));
-  chk(dalloc(&m->d_rank, n));
-  chk(dalloc(&m->d_slot_atom, n));
-  chk(dalloc(&m->d_sbin, n));
-  chk(dalloc(&m->d_loc, n));
-  chk(dalloc(&m->d_islot, n));
-  chk(dalloc(&m->d_pcount, n));
-  chk(dalloc(&m->d_spos, n));
-  chk(dalloc(&m->d_stg, n));
-  chk(dalloc(&m->d_bin_count, (size_t)m->max_bins));
-  chk(dalloc(&m->d_bin_start, (size_t)m->max_bins + 1));
-  chk(dalloc(&m->d_cmstart, (size_t)m->max_bins));
-  chk(dalloc(&m->d_order, n));
-  chk(dalloc(&m->d_nbr_rad, n * m->max_rad));
-  chk(dalloc(&m->d_nbr_ang, n * m->max_ang));
-  chk(dalloc(&m->d_rad_off, n * (m->S + 1)));
-  chk(dalloc(&m->d_ang_off, n * (m->S + 1)));
-  chk(dalloc(&m->d_angpos, n * m->max_ang));
-  chk(dalloc(&m->d_contrib, n * m->max_rad));
-  chk(dalloc(&m->d_self, 3 * n));
-  m->max_part = max_atoms / kTileAtoms + 2 * kMaxSpecies + 8;
-  chk(dalloc(&m->d_part, (size_t)m->max_part));
-  chk(dalloc(&m->d_x, n * m->stride));
-  chk(dalloc(&m->d_g, n * m->stride));
-  chk(dalloc(&m->d_e, n));
-  if (m->extra && max_mm > 0) chk(dalloc(&m->d_mm_part, mm_partial_floats(max_atoms, max_mm)));
-  if (m->charges) chk(dalloc(&m->d_q, n));
-  if (e == hipSuccess) e = hipMemset(m->d_bin_count, 0, (size_t)m->max_bins * sizeof(int));
-  if (e == hipSuccess) e = hipMemset(m->d_x, 0, n * m->stride * sizeof(float));
-  if (e == hipSuccess) e = hipMemset(m->d_g, 0, n * m->stride * sizeof(float));
+  Workspace w = workspace_caps(*m, max_atoms, max_systems, max_mm, max_rad_nbr ? max_rad_nbr : 128,
+                               max_ang_nbr ? max_ang_nbr : 64);
+  const size_t bytes = carve_workspace(*m, w, nullptr);
+  hipError_t e = hipMalloc(&m->d_ws_base, bytes);
   if (e == hipSuccess) {
-    size_t stage = 3 * n + 8;
+    carve_workspace(*m, w, static_cast<char*>(m->d_ws_base));
+    static_cast<Workspace&>(*m) = w;
+    // the histogram starts from zero (every call leaves it cleared); descriptor
+    // padding columns stay zero
+    e = hipMemset(m->d_bin_count, 0, (size_t)m->max_bins * sizeof(int));
+  }
+  if (e == hipSuccess) e = hipMemset(m->d_x, 0, (size_t)max_atoms * m->stride * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->d_g, 0, (size_t)max_atoms * m->stride * sizeof(float));
+  if (e == hipSuccess) {
+    size_t stage = 3 * (size_t)max_atoms + 8;
     if ((size_t)max_systems + 1 > stage) stage = (size_t)max_systems + 1;
     e = hipHostMalloc(reinterpret_cast<void**>(&m->h_stage), stage * sizeof(int), hipHostMallocDefault);
   }
@@ -406,7 +441,9 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   return NNP_OK;
 }
 
-namespace {
+}  // extern "C"
+
+namespace nnp {
 
 // Box checks and the cell grid of a periodic call.
 nnp_status setup_periodic(nnp_model* m, const float* box) {
@@ -487,7 +524,9 @@ nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float
   return NNP_OK;
 }
 
-}  // namespace
+}  // namespace nnp
+
+extern "C" {
 
 namespace {
 

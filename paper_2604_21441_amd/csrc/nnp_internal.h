@@ -151,36 +151,14 @@ struct MlpArgs {
   int phi_col;             // column of x holding the MM potential (models with charges)
 };
 
-}  // namespace nnp
-
-// The model object.
-struct nnp_model {
-  int device = 0;
-  nnp_precision prec = NNP_FP32;
-  int S = 0, P = 0, D = 0, Din = 0, stride = 0, n_members = 1, extra = 0;
-  int charges = 0;                      // second network output: an atomic charge in the MM potential
-  std::vector<int> species;             // atomic numbers, ascending
-  std::vector<int> widths;              // unpadded widths
-  float celu_alpha = 0.1f;
-  nnp::DescParams dp{};
-  int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
-  int mlp_mixed = 0;                    // the species with the fewest atoms uses one column tile
-  std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
-  int force_variant[nnp::kTuneStages] = {-1, -1, -1, -1};   // set while timing candidates
-  int pinned[nnp::kTuneStages] = {-1, -1, -1, -1};          // nnp_set_variant
-  int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
-  std::vector<float> w_host;            // canonical FP32 weights, draw order
-
-  // device weights
-  void* d_wmat = nullptr;
-  float* d_wvec = nullptr;
-  int64_t mat_per_species = 0, vec_per_species = 0;
-
+// Per-call device workspace: capacities and the arrays sized from them.
+// nnp_reserve carves it out of one allocation; the no-allocation entry
+// point carves the same layout out of a static device array for one call.
+struct Workspace {
   // capacities
   int max_atoms = 0, max_sys = 0, max_mm = 0, max_rad = 0, max_ang = 0, max_bins = 0;
-  bool reserved = false;
 
-  // workspace (device)
+  // device arrays
   int* d_idx = nullptr;        // NNP-local atom -> atom index
   int* d_sigma = nullptr;      // NNP-local atom -> species
   int* d_sys = nullptr;        // NNP-local atom -> system (batched)
@@ -214,6 +192,35 @@ struct nnp_model {
   float* d_e = nullptr;
   float* d_mm_part = nullptr;  // MM channel per-workgroup partials [mm_partial_floats(max_atoms, max_mm)]
   float* d_q = nullptr;        // predicted atomic charges (member mean) [max_atoms], models with charges
+};
+
+}  // namespace nnp
+
+// The model object.
+struct nnp_model : nnp::Workspace {
+  int device = 0;
+  nnp_precision prec = NNP_FP32;
+  int S = 0, P = 0, D = 0, Din = 0, stride = 0, n_members = 1, extra = 0;
+  int charges = 0;                      // second network output: an atomic charge in the MM potential
+  std::vector<int> species;             // atomic numbers, ascending
+  std::vector<int> widths;              // unpadded widths
+  float celu_alpha = 0.1f;
+  nnp::DescParams dp{};
+  int mlp_cols = 1;                     // column tiles (16 atoms each) per network workgroup
+  int mlp_mixed = 0;                    // the species with the fewest atoms uses one column tile
+  std::map<std::pair<int, int>, int> tuned;   // (stage, size bucket) -> variant
+  int force_variant[nnp::kTuneStages] = {-1, -1, -1, -1};   // set while timing candidates
+  int pinned[nnp::kTuneStages] = {-1, -1, -1, -1};          // nnp_set_variant
+  int net_kind = 0;                     // 0 water (128-160-128-96), 1 hcno (384/416-256-192-160)
+  std::vector<float> w_host;            // canonical FP32 weights, draw order
+
+  // device weights
+  void* d_wmat = nullptr;
+  float* d_wvec = nullptr;
+  int64_t mat_per_species = 0, vec_per_species = 0;
+
+  bool reserved = false;
+  void* d_ws_base = nullptr;    // the one allocation every Workspace array of nnp_reserve lives in
   int* d_status = nullptr;
   int* h_stage = nullptr;      // pinned staging for topology uploads
 
@@ -263,6 +270,22 @@ int adjoint_variant(const nnp_model& m, int n);
 int stage_variant(const nnp_model& m, int stage, int n);
 constexpr int kStageVariants[kTuneStages] = {4, 3, 8, 3};
 int size_bucket(int n);
+
+// workspace (api.cpp): capacities for a call of up to max_atoms atoms, and the
+// layout of every array at 256-byte aligned offsets from base (null: measure
+// only); returns the bytes the layout spans.
+Workspace workspace_caps(const nnp_model& m, int max_atoms, int max_systems, int max_mm, int max_rad, int max_ang);
+size_t carve_workspace(const nnp_model& m, Workspace& w, char* base);
+// geometry and the stage sequence of one call (api.cpp)
+nnp_status setup_periodic(nnp_model* m, const float* box);
+nnp_status run_path(nnp_model* m, int n, const float* pos, int n_mm, const float* mm_pos, const float* mm_q,
+                    double* energies, int n_sys, double* forces, double* mm_forces, int accumulate,
+                    int assign_forces, int n_atoms, int n_pairs, const int* pairs, hipStream_t st);
+
+// noalloc.hip: size of the static workspace of nnp_compute_noalloc, and the
+// once-per-device lookup of its device address (called by nnp_create)
+constexpr size_t kNoallocScratchBytes = size_t(32) << 20;
+nnp_status noalloc_scratch_setup(int device);
 
 // error helpers (api.cpp)
 nnp_status set_error(nnp_status s, const std::string& msg);

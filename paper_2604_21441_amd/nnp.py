@@ -17,7 +17,7 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_pairs", "nnp_compute_batch", "nnp_get_status",
+    "NNPError", "nnp_create", "nnp_reserve", "nnp_compute", "nnp_compute_pairs", "nnp_compute_batch", "nnp_compute_noalloc", "nnp_get_status",
     "nnp_read_buffer", "nnp_destroy", "nnp_profile_enable", "nnp_profile_read", "nnp_set_graph", "nnp_autotune", "nnp_set_variant", "nnp_get_variants", "nnp_me_coupling", "nnp_set_links", "nnp_status_string", "nnp_last_error", "nnp_version",
     "make_config", "NNPModel", "NNPEnergy",
 ]
@@ -189,6 +189,18 @@ def nnp_compute_batch(h, offsets, pos: torch.Tensor, Z, energies: torch.Tensor, 
                                     _dptr(energies, torch.float64, "energies"),
                                     _dptr(forces, torch.float64, "forces"), _stream(stream))
     _check(st, "nnp_compute_batch")
+
+
+def nnp_compute_noalloc(h, pos: torch.Tensor, Z, box, energy: torch.Tensor, forces: torch.Tensor,
+                        stream=None) -> None:
+    """nnp_compute for an all-NNP system on the library's static workspace (allocates nothing)."""
+    n = pos.shape[0]
+    Za, Zp = _host(Z, np.int32, "Z")
+    Ba, Bp = _host(box, np.float32, "box")
+    st = L.load().nnp_compute_noalloc(h, n, _dptr(pos, torch.float32, "pos"), Zp, Bp,
+                                      _dptr(energy, torch.float64, "energy"), _dptr(forces, torch.float64, "forces"),
+                                      _stream(stream))
+    _check(st, "nnp_compute_noalloc")
 
 
 def nnp_get_status(h, stream=None) -> int:
