@@ -185,8 +185,10 @@ nnp_status nnp_compute(nnp_model* m, int32_t n_atoms, const float* pos, const in
  * must hold every pair of index-group atoms closer than the radial cutoff;
  * with such a list the neighbour lists, and so the results, are bit-identical
  * to nnp_compute's.  A self pair, an out-of-range index or a repeated pair
- * sets the device status (NNP_EINVAL from nnp_get_status).  Link atoms are
- * not supported on this path (NNP_ESTATE); max_rad_nbr must be <= 256.
+ * sets the device status (NNP_EINVAL from nnp_get_status).  Link atoms
+ * (nnp_set_links) are not atoms of the system, so the list cannot name them:
+ * their pairs with the NNP atoms are found by a direct scan with the same
+ * predicate (n_links x n_nnp distance tests).  max_rad_nbr must be <= 256.
  */
 nnp_status nnp_compute_pairs(nnp_model* m, int32_t n_atoms, const float* pos, const int32_t* Z_host,
                              const float* box_host, int32_t n_nnp, const int32_t* nnp_idx_host, int32_t n_pairs,
@@ -195,16 +197,29 @@ nnp_status nnp_compute_pairs(nnp_model* m, int32_t n_atoms, const float* pos, co
                              hipStream_t stream);
 
 /*
- * Energies and forces of n_sys independent open (non-periodic) systems packed
- * back to back: system s owns atoms [atom_offsets_host[s], atom_offsets_host[s+1]).
- * All atoms are NNP atoms.  energies [n_sys] FP64, forces [total][3] FP64, both
- * overwritten.  Z_host NULL reuses the previous batched call's topology.
+ * Energies and forces of n_sys independent systems packed back to back (the
+ * paper's performance section traces the cost of small systems to per-step
+ * launch and dispatch overhead; batching replicas, lambda-windows or
+ * conformers into one call amortises it): system s owns atoms
+ * [atom_offsets_host[s], atom_offsets_host[s+1]).  All atoms are NNP atoms.
+ *   boxes_host  [n_sys][3] host, orthorhombic box lengths per system (each
+ *               above 2*rc_rad; minimum image within the system), a row of
+ *               zeros for an open system; NULL: every system is open.
+ *   energies    [n_sys] FP64, forces [total][3] FP64 (device), overwritten.
+ * Z_host NULL reuses the previous batched call's topology (atomic numbers and
+ * offsets).  Each system's neighbours are found by one scan over its own
+ * atoms (per-system cost grows with the square of its size: meant for many
+ * small systems; a large box is faster through nnp_compute's cell list).
  * One neighbour search, one descriptor launch, one grouped network launch and
- * one adjoint launch cover all systems.
+ * one adjoint launch cover all systems.  The boxes are kept in device memory:
+ * a call whose boxes differ from the previous call's uploads them (this
+ * synchronises the stream and is refused under stream capture, as a topology
+ * change is) and replays the captured graph.  A batched call has no index
+ * group, so link atoms (nnp_set_links) do not apply to it.
  */
 nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host,
-                             const float* pos, const int32_t* Z_host, double* energies,
-                             double* forces, hipStream_t stream);
+                             const float* pos, const int32_t* Z_host, const float* boxes_host,
+                             double* energies, double* forces, hipStream_t stream);
 
 /*
  * nnp_compute without any allocation, for callers that cannot allocate
@@ -240,7 +255,8 @@ nnp_status nnp_compute_noalloc(nnp_model* m, int32_t n_atoms, const float* pos, 
  * as an NNP atom, appended after the index group.  Its force is passed on to
  * the ML and MM atoms by the chain rule:
  *   F_MM += (d/|u|) (F_L - (F_L.u^) u^),  F_ML += F_L - that,  u = r_MM - r_ML.
- * Applies to later nnp_compute calls (not to batched calls); n_links = 0
+ * Applies to later nnp_compute and nnp_compute_pairs calls (a batched call
+ * has no index group); n_links = 0
  * removes them.  The paper's defaults are link_Z = 1 and d = 1 Angstrom.
  * Allocates (device arrays of the link list): call outside graph capture.
  */
@@ -273,8 +289,11 @@ typedef enum {
   NNP_BUF_ORDER = 10,     /* int32 [n_nnp]: slots in the order the per-atom
                              kernels visit them: bin by bin, species by species
                              within a bin, ascending slot within a species     */
-  NNP_BUF_CHARGE = 11     /* float [n_nnp] predicted atomic charges per sorted
+  NNP_BUF_CHARGE = 11,    /* float [n_nnp] predicted atomic charges per sorted
                              slot (models with a charge output; else EINVAL)  */
+  NNP_BUF_GRAPH = 12      /* int32 [3]: HIP graphs instantiated, graphs updated
+                             in place for a call with new arguments, replays
+                             of an unchanged graph (counts since creation)   */
 } nnp_buffer;
 
 /*
@@ -348,12 +367,19 @@ nnp_status nnp_get_variants(nnp_model* m, int32_t* chosen);
 
 /*
  * HIP-graph replay (enabled by default).  The first call of a configuration
- * (same output/input pointers, sizes, flags and box) is captured into a HIP
- * graph; later identical calls replay it with one launch.  Device memory
- * contents (positions, topology arrays) may change between replays.  Calls
- * made while the stream is already capturing, or while stage timing is on,
- * launch their kernels directly.  enable = 0 turns replay off and frees the
- * cached graph.
+ * is captured into a HIP graph; a later call with the same arguments (device
+ * pointers, sizes, flags and box) replays it with one launch.  A call whose
+ * arguments differ (a new box every step under a barostat, other output
+ * buffers) is captured again and the instantiated graph is updated in place
+ * with the new kernel arguments (hipGraphExecUpdate), which costs far less
+ * than building a new graph; a graph is only rebuilt when the update is
+ * refused (a different sequence of kernels, e.g. another cell grid).  The
+ * per-system boxes of nnp_compute_batch live in device memory and never
+ * change the graph.  Device memory contents (positions, topology arrays) may
+ * change between replays.  Calls made while the stream is already capturing,
+ * or while stage timing is on, launch their kernels directly.  enable = 0
+ * turns replay off and frees the cached graph.  NNP_BUF_GRAPH counts builds,
+ * updates and replays.
  */
 nnp_status nnp_set_graph(nnp_model* m, int32_t enable);
 

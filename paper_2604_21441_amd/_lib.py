@@ -38,6 +38,7 @@ NNP_BUF_DEDX = 8
 NNP_BUF_GRID = 9
 NNP_BUF_ORDER = 10
 NNP_BUF_CHARGE = 11
+NNP_BUF_GRAPH = 12
 
 # nnp_stage
 STAGES = ["cells", "neighbours", "descriptor", "mm", "network", "energy", "adjoint", "gather", "mm_adjoint"]
@@ -76,7 +77,7 @@ SIGNATURES = {
                               _P, _P, _P, C.c_int32, _P]),
     "nnp_compute_pairs": (C.c_int, [_P, C.c_int32, _P, _I32P, _F32P, C.c_int32, _I32P, C.c_int32, _P, C.c_int32,
                                     _P, _P, _P, _P, _P, C.c_int32, _P]),
-    "nnp_compute_batch": (C.c_int, [_P, C.c_int32, _I32P, _P, _I32P, _P, _P, _P]),
+    "nnp_compute_batch": (C.c_int, [_P, C.c_int32, _I32P, _P, _I32P, _F32P, _P, _P, _P]),
     "nnp_compute_noalloc": (C.c_int, [_P, C.c_int32, _P, _I32P, _F32P, _P, _P, _P]),
     "nnp_get_status": (C.c_int, [_P, _P]),
     "nnp_read_buffer": (C.c_int, [_P, C.c_int, _P, C.c_size_t, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _P]),

@@ -100,6 +100,7 @@ size_t carve_workspace(const nnp_model& m, Workspace& w, char* base) {
   if (m.extra && w.max_mm > 0) take(w.d_mm_part, mm_partial_floats(w.max_atoms, w.max_mm));
   w.d_q = nullptr;
   if (m.charges) take(w.d_q, n);
+  take(w.d_sys_box, 2 * (size_t)w.max_sys);
   return (off + 255) & ~size_t(255);
 }
 
@@ -147,6 +148,10 @@ std::vector<uint8_t> make_key(const T&... parts) {
 
 // Run `launch(stream)` directly, or replay / capture it as a HIP graph.
 // Identical calls (same key) replay one graph: one launch instead of ~15.
+// A call with another key (a new box, other output buffers) captures its
+// launches again and first tries to update the instantiated graph in place
+// (hipGraphExecUpdate: same kernels in the same order, new arguments), which
+// is far cheaper than instantiating; only if that fails is the graph rebuilt.
 // Capture happens on the model's own stream (the caller's may be the legacy
 // default stream, which cannot be captured); the graph runs on the caller's.
 template <typename F>
@@ -161,7 +166,6 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
     ++m->graph_replays;
     return NNP_OK;
   }
-  drop_graph(m);
   HIP_TRY(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal), "graph capture");
   nnp_status s = launch(m->cap_stream);
   hipGraph_t g = nullptr;
@@ -171,6 +175,20 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
     return s;
   }
   if (e != hipSuccess) return hip_error(e, "graph capture");
+  if (m->graph_exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(m->graph_exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      if (m->graph) (void)hipGraphDestroy(m->graph);
+      m->graph = g;
+      m->graph_key = std::move(key);
+      ++m->graph_updates;
+      HIP_TRY(hipGraphLaunch(m->graph_exec, st), "graph launch");
+      return NNP_OK;
+    }
+    (void)hipGetLastError();
+  }
+  drop_graph(m);
   e = hipGraphInstantiate(&m->graph_exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
@@ -179,7 +197,7 @@ nnp_status dispatch(nnp_model* m, std::vector<uint8_t> key, hipStream_t st, F la
   }
   m->graph = g;
   m->graph_key = std::move(key);
-  m->graph_replays = 0;
+  ++m->graph_builds;
   HIP_TRY(hipGraphLaunch(m->graph_exec, st), "graph launch");
   return NNP_OK;
 }
@@ -192,18 +210,30 @@ void free_workspace(nnp_model* m) {
   m->h_stage = nullptr;
   m->reserved = false;
   m->topo_mode = -1;
+  m->topo_boxes.clear();
   drop_graph(m);
 }
 
 int descriptor_length(int S) { return kRadShifts * S + kAngShifts * kAngSects * (S * (S + 1) / 2); }
 
-// Upload the host topology through the pinned staging buffer.
-nnp_status upload_ints(nnp_model* m, int* dst, const int* src, int n, hipStream_t st) {
+// Upload host topology data (n 4-byte words) through the pinned staging
+// buffer, ordered after the stream's earlier work.  This synchronises the
+// stream, so it is refused while the stream is being captured.
+nnp_status upload_words(nnp_model* m, void* dst, const void* src, int n, hipStream_t st) {
   if (n <= 0) return NNP_OK;
-  std::memcpy(m->h_stage, src, sizeof(int) * (size_t)n);
-  HIP_TRY(hipMemcpyAsync(dst, m->h_stage, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, st), "topology upload");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (st != nullptr && (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone))
+    return set_error(NNP_ESTATE,
+                     "a new topology (atomic numbers, index group, offsets or batch boxes) cannot be uploaded while "
+                     "the stream is being captured: make one call with it outside the capture first");
+  std::memcpy(m->h_stage, src, 4 * (size_t)n);
+  HIP_TRY(hipMemcpyAsync(dst, m->h_stage, 4 * (size_t)n, hipMemcpyHostToDevice, st), "topology upload");
   HIP_TRY(hipStreamSynchronize(st), "topology upload");
   return NNP_OK;
+}
+
+nnp_status upload_ints(nnp_model* m, int* dst, const int* src, int n, hipStream_t st) {
+  return upload_words(m, dst, src, n, st);
 }
 
 nnp_status species_of(const nnp_model* m, int z, int* out) {
@@ -429,7 +459,7 @@ nnp_status nnp_reserve(nnp_model* m, int32_t max_atoms, int32_t max_systems, int
   if (e == hipSuccess) e = hipMemset(m->d_g, 0, (size_t)max_atoms * m->stride * sizeof(float));
   if (e == hipSuccess) {
     size_t stage = 3 * (size_t)max_atoms + 8;
-    if ((size_t)max_systems + 1 > stage) stage = (size_t)max_systems + 1;
+    if (8 * (size_t)max_systems + 8 > stage) stage = 8 * (size_t)max_systems + 8;
     e = hipHostMalloc(reinterpret_cast<void**>(&m->h_stage), stage * sizeof(int), hipHostMallocDefault);
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -447,6 +477,7 @@ namespace nnp {
 
 // Box checks and the cell grid of a periodic call.
 nnp_status setup_periodic(nnp_model* m, const float* box) {
+  m->geo = Geometry{};
   Geometry& g = m->geo;
   g.periodic = 1;
   const float rc = m->dp.rc_rad;
@@ -555,7 +586,6 @@ nnp_status compute_single(nnp_model* m, int32_t n_atoms, const float* pos, const
   const bool pair_mode = pairs != nullptr || n_pairs != 0;
   if (pair_mode) {
     if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return set_error(NNP_EINVAL, "bad pair list");
-    if (m->n_links_dev > 0) return set_error(NNP_ESTATE, "link atoms are not supported with a caller's pair list");
     if (m->max_rad > kPairRowMax)
       return set_error(NNP_EINVAL, "pair lists need max_rad_nbr <= " + std::to_string(kPairRowMax));
   }
@@ -681,7 +711,8 @@ nnp_status nnp_compute_pairs(nnp_model* m, int32_t n_atoms, const float* pos, co
 }
 
 nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_offsets_host, const float* pos,
-                             const int32_t* Z_host, double* energies, double* forces, hipStream_t stream) {
+                             const int32_t* Z_host, const float* boxes_host, double* energies, double* forces,
+                             hipStream_t stream) {
   if (!m) return set_error(NNP_EINVAL, "null model");
   if (!m->reserved) return set_error(NNP_ESTATE, "nnp_reserve must be called first");
   if (m->extra) return set_error(NNP_EINVAL, "batched calls do not take MM charges");
@@ -693,6 +724,25 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
   const int n = atom_offsets_host[n_sys];
   if (n > m->max_atoms) return set_error(NNP_ECAPACITY, "total atoms exceed the reserved capacity");
   if (!energies || (n > 0 && (!pos || !forces))) return set_error(NNP_EINVAL, "null output or position array");
+
+  // per-system boxes: (L, 1/L) in FP32 per system, zeros for an open system
+  std::vector<float> boxes;
+  if (boxes_host) {
+    boxes.assign(8 * (size_t)n_sys, 0.f);
+    const float rc = m->dp.rc_rad;
+    for (int s = 0; s < n_sys; ++s) {
+      const float* b = boxes_host + 3 * (size_t)s;
+      const bool open = b[0] == 0.f && b[1] == 0.f && b[2] == 0.f;
+      if (open) continue;
+      for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(b[k]) || !(b[k] > 2.f * rc))
+          return set_error(NNP_EBOX, "system " + std::to_string(s) + ": box length " + std::to_string(b[k]) +
+                                         " must exceed twice the cutoff (or the whole row be 0 for an open system)");
+        boxes[8 * (size_t)s + k] = b[k];
+        boxes[8 * (size_t)s + 4 + k] = 1.0f / b[k];
+      }
+    }
+  }
 
   if (Z_host) {
     bool same = m->topo_mode == 1 && m->topo_n_atoms == n && (int)m->topo_offsets.size() == n_sys + 1 &&
@@ -718,14 +768,23 @@ nnp_status nnp_compute_batch(nnp_model* m, int32_t n_sys, const int32_t* atom_of
       m->topo_Z.assign(Z_host, Z_host + n);
       m->topo_offsets.assign(atom_offsets_host, atom_offsets_host + n_sys + 1);
       m->topo_idx.clear();
+      m->topo_boxes.clear();
     }
   } else if (m->topo_mode != 1 || m->topo_n_atoms != n || (int)m->topo_offsets.size() != n_sys + 1) {
     return set_error(NNP_ESTATE, "Z_host is NULL but no matching batched topology was given before");
+  }
+  // the boxes live in device memory, so a captured graph stays valid when they change
+  if (boxes_host && boxes != m->topo_boxes) {
+    nnp_status st = upload_words(m, m->d_sys_box, boxes.data(), 8 * n_sys, stream);
+    if (st != NNP_OK) return st;
+    m->topo_boxes = boxes;
   }
   m->geo = Geometry{};
   m->geo.periodic = 0;
   m->geo.n_bins = n_sys;
   m->geo.nc[0] = m->geo.nc[1] = m->geo.nc[2] = 1;
+  m->geo.sys_box = boxes_host ? m->d_sys_box : nullptr;
+  m->geo.sbin = m->d_sbin;
   if (m->S * n_sys > m->max_bins) return set_error(NNP_ECAPACITY, "too many systems for the reserved bins");
   m->last_n = n;
   auto launch = [=](hipStream_t s) -> nnp_status {
@@ -794,6 +853,12 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
       count = 4;
       break;
     }
+    case NNP_BUF_GRAPH: {
+      auto clamp = [](int64_t v) { return (int)(v > 0x7fffffff ? 0x7fffffff : v); };
+      tmp = {clamp(m->graph_builds), clamp(m->graph_updates), clamp(m->graph_replays)};
+      count = 3;
+      break;
+    }
     default: return set_error(NNP_EINVAL, "unknown buffer");
   }
   *elems = count;
@@ -802,7 +867,7 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
   if (bytes > capacity_bytes) bytes = capacity_bytes;
   if (bytes == 0) return NNP_OK;
   if (!dst_host) return set_error(NNP_EINVAL, "null destination");
-  if (!tmp.empty() || which == NNP_BUF_NBR_COUNT || which == NNP_BUF_GRID) {
+  if (!tmp.empty() || which == NNP_BUF_NBR_COUNT || which == NNP_BUF_GRID || which == NNP_BUF_GRAPH) {
     std::memcpy(dst_host, tmp.data(), bytes);
   } else {
     HIP_TRY(hipMemcpy(dst_host, src, bytes, hipMemcpyDeviceToHost), "nnp_read_buffer");

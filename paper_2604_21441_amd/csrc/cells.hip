@@ -601,6 +601,7 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
   const int lane = threadIdx.x;
   const float4 pi = a.spos[i];
   const int sb = a.sbin[i];
+  const MinImage mi = min_image_at(g, i);
   // Stencil cells in ascending id order: per dimension the (wrapped)
   // coordinates {c-1, c, c+1} are sorted, and ids are lexicographic in
   // (x, y, z).  Lane l < nst takes the l-th of them.
@@ -719,17 +720,7 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
       // straight-line test (invalid lanes read the centre's own position and
       // are masked), so the ballots take the comparison masks directly
       const bool valid = j >= 0 && j != i;
-      float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-      if (g.periodic) {
-        float sx = rintf(dx * g.inv_box[0]);
-        float sy = rintf(dy * g.inv_box[1]);
-        float sz = rintf(dz * g.inv_box[2]);
-        float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-        dx = dx - tx; dy = dy - ty; dz = dz - tz;
-      }
-      float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-      float r2 = xx + yy;
-      r2 = r2 + zz;
+      const float r2 = pair_r2_exact(pi, pj, mi);
       const bool in_r = valid && r2 < a.rc2;
       const uint64_t mr = __builtin_amdgcn_ballot_w64(in_r);
       const int pr = nr + below(mr);
@@ -776,6 +767,7 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g,
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int cell = b / K, part = b - cell * K;
   const int lane = threadIdx.x;
+  const MinImage mi = min_image_of_system(g, cell);   // a batch's bins are its systems
   // stencil cells in ascending id order (see k_neighbours)
   int nst = 1;
   int my_cell = cell;
@@ -881,17 +873,7 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g,
           const int i = s_cid[ci];
           bool in_r = false, in_a = false;
           if (j >= 0 && j != i) {
-            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-            if (g.periodic) {
-              float sx = rintf(dx * g.inv_box[0]);
-              float sy = rintf(dy * g.inv_box[1]);
-              float sz = rintf(dz * g.inv_box[2]);
-              float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-              dx = dx - tx; dy = dy - ty; dz = dz - tz;
-            }
-            float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-            float r2 = xx + yy;
-            r2 = r2 + zz;
+            const float r2 = pair_r2_exact(pi, pj, mi);
             in_r = r2 < a.rc2;
             in_a = r2 < a.rca2;
           }
@@ -937,18 +919,7 @@ __global__ __launch_bounds__(64) void k_neighbours_cell(NeighArgs a, Geometry g,
 // species-major), derives the species segments and the angular sub-list, so
 // the lists are exactly the ones the cell-list search builds.
 __device__ __forceinline__ float pair_r2(const float4& pi, const float4& pj, const Geometry& g) {
-#pragma clang fp contract(off)
-  float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-  if (g.periodic) {
-    float sx = rintf(dx * g.inv_box[0]);
-    float sy = rintf(dy * g.inv_box[1]);
-    float sz = rintf(dz * g.inv_box[2]);
-    float tx = sx * g.box[0], ty = sy * g.box[1], tz = sz * g.box[2];
-    dx = dx - tx; dy = dy - ty; dz = dz - tz;
-  }
-  float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-  float r2 = xx + yy;
-  return r2 + zz;
+  return pair_r2_exact(pi, pj, min_image_of_system(g, 0));   // one system: the call's box or none
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_scatter(const int* __restrict__ pairs, int n_pairs,
@@ -971,6 +942,27 @@ __global__ __launch_bounds__(kBlock) void k_pairs_scatter(const int* __restrict_
   const int pa = atomicAdd(&pcount[sa], 1), pb = atomicAdd(&pcount[sb], 1);
   if (pa < max_rad) rad[(int64_t)sa * max_rad + pa] = sb;
   if (pb < max_rad) rad[(int64_t)sb * max_rad + pb] = sa;
+}
+
+// Link atoms (eq. 4) are not atoms of the system, so a caller's pair list
+// cannot name them: one wavefront per link atom tests it against every NNP
+// atom with the same predicate and appends each pair within the cutoff to
+// both rows.  A pair of two link atoms is added by the one with the lower
+// index.  The NNP-local indices of the link atoms are [n - n_links, n).
+__global__ __launch_bounds__(64) void k_link_pairs(int n, int n_links, const int* __restrict__ islot,
+                                                   const float4* __restrict__ spos, Geometry g, float rc2,
+                                                   int* __restrict__ rad, int* __restrict__ pcount, int max_rad) {
+  const int tl = n - n_links + (int)blockIdx.x;
+  const int sl = islot[tl];
+  const float4 pl = spos[sl];
+  for (int t = threadIdx.x; t < n; t += 64) {
+    if (t >= n - n_links && t <= tl) continue;
+    const int st = islot[t];
+    if (!(pair_r2(pl, spos[st], g) < rc2)) continue;
+    const int pa = atomicAdd(&pcount[sl], 1), pb = atomicAdd(&pcount[st], 1);
+    if (pa < max_rad) rad[(int64_t)sl * max_rad + pa] = st;
+    if (pb < max_rad) rad[(int64_t)st * max_rad + pb] = sl;
+  }
 }
 
 // One wavefront per slot: bitonic sort of the row (padded to a power of two,
@@ -1184,6 +1176,10 @@ hipError_t launch_pair_lists(nnp_model& m, int n, int n_atoms, int n_pairs, cons
     hipLaunchKernelGGL(k_pairs_scatter, dim3(blocks_for(n_pairs, kBlock)), dim3(kBlock), 0, st, pairs, n_pairs,
                        m.d_loc, n_atoms, m.d_islot, m.d_spos, m.geo, m.dp.rc_rad * m.dp.rc_rad, m.d_nbr_rad,
                        m.d_pcount, m.max_rad, m.d_status);
+  }
+  if (m.n_links_dev > 0) {
+    hipLaunchKernelGGL(k_link_pairs, dim3(m.n_links_dev), dim3(64), 0, st, n, m.n_links_dev, m.d_islot, m.d_spos,
+                       m.geo, m.dp.rc_rad * m.dp.rc_rad, m.d_nbr_rad, m.d_pcount, m.max_rad);
   }
   NeighArgs a;
   a.order = m.d_order;

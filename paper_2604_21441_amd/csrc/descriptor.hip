@@ -38,13 +38,13 @@ struct Geo {
   float dx, dy, dz, r, ir;
 };
 
-__device__ __forceinline__ Geo displacement(const float4& pi, const float4& pj, const Geometry& g) {
+__device__ __forceinline__ Geo displacement(const float4& pi, const float4& pj, const MinImage& b) {
   Geo o;
   float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-  if (g.periodic) {
-    dx -= g.box[0] * rintf(dx * g.inv_box[0]);
-    dy -= g.box[1] * rintf(dy * g.inv_box[1]);
-    dz -= g.box[2] * rintf(dz * g.inv_box[2]);
+  if (b.on) {
+    dx -= b.L[0] * rintf(dx * b.iL[0]);
+    dy -= b.L[1] * rintf(dy * b.iL[1]);
+    dz -= b.L[2] * rintf(dz * b.iL[2]);
   }
   float r2 = dx * dx + dy * dy + dz * dz;
   float ir = rsq(r2);
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
   const int lane = threadIdx.x;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
+  const MinImage mi = min_image_at(geo, i);
   const int S1 = p.S + 1;
   const int* roff = a.rad_off + (int64_t)i * S1;
   const int* aoff = a.ang_off + (int64_t)i * S1;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
     if (my_b >= 0) {
       const int t1 = roff[my_b + 1];
       for (int t = roff[my_b] + my_rank; t < t1; t += my_len) {
-        Geo d = displacement(pi, a.spos[rrow[t]], geo);
+        Geo d = displacement(pi, a.spos[rrow[t]], mi);
         float fc = 0.5f * cos_rev(d.r * c.inv2rc) + 0.5f;
 #pragma unroll
         for (int k = 0; k < kRadShifts; ++k) {
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(64) void k_desc_fwd(FwdArgs a, DescParams p, Geomet
   // angular neighbour geometry
   const int na = aoff[p.S];
   for (int u = lane; u < na; u += 64) {
-    Geo d = displacement(pi, a.spos[arow[u]], geo);
+    Geo d = displacement(pi, a.spos[arow[u]], mi);
     gux[u] = d.dx * d.ir;
     guy[u] = d.dy * d.ir;
     guz[u] = d.dz * d.ir;
@@ -333,6 +334,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
   const int S1 = p.S + 1;
   const int ii = valid ? a.order[li] : 0;
   const float4 pi = a.spos[ii];
+  const MinImage mi = min_image_at(geo, ii);
   const int* roff = a.rad_off + (int64_t)ii * S1;
   const int* aoff = a.ang_off + (int64_t)ii * S1;
   const int* rrow = a.rad + (int64_t)ii * a.max_rad;
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
   // angular neighbour geometry of this row's atom
   const int na = valid ? aoff[p.S] : 0;
   for (int u = sub; u < na; u += L) {
-    Geo d = displacement(pi, a.spos[arow[u]], geo);
+    Geo d = displacement(pi, a.spos[arow[u]], mi);
     G[u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
     W[u] = (0.5f * cos_rev(d.r * c.inv2rca) + 0.5f) * p.sq_pref;
   }
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
     const int t1 = valid ? roff[s + 1] : 0;
     for (int t = (valid ? roff[s] : 0) + sub; t < t1; t += L) {
 #pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
-      Geo d = displacement(pi, a.spos[rrow[t]], geo);
+      Geo d = displacement(pi, a.spos[rrow[t]], mi);
       const float fc = fmaf(0.5f, cos_rev(d.r * c.inv2rc), 0.5f);
       const float rs = d.r * p.sq_eta_r;
 #pragma unroll
@@ -501,6 +503,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   const int i = valid ? a.order[li] : 0;
   const Consts c = make_consts(p);
   const float4 pi = a.spos[i];
+  const MinImage mi = min_image_at(geo, i);
   const int S1 = p.S + 1;
   const int nr = valid ? a.rad_off[(int64_t)i * S1 + p.S] : 0;
   const int na = valid ? a.ang_off[(int64_t)i * S1 + p.S] : 0;
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   // 3. angular neighbour geometry (before the barrier, together with 1.)
   for (int u = lane; u < na; u += LANES) {
     const float4 pj = a.spos[arow[u]];
-    Geo d = displacement(pi, pj, geo);
+    Geo d = displacement(pi, pj, mi);
     const float arg = d.r * c.inv2rca;
     G1[u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
     G2[u] = make_float4(fmaf(0.5f, cos_rev(arg), 0.5f) * p.sq_pref, c.dfc_a * sin_rev(arg) * p.sq_pref, d.ir,
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
 #pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
       const float4 pj = a.spos[rrow[t]];
       const int sj = __float_as_int(pj.w);
-      Geo d = displacement(pi, pj, geo);
+      Geo d = displacement(pi, pj, mi);
       const float arg = d.r * c.inv2rc;
       const float fc = fmaf(0.5f, cos_rev(arg), 0.5f);
       const float dfc = c.dfc_r * sin_rev(arg);

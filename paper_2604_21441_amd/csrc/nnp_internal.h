@@ -106,13 +106,66 @@ struct DescParams {
 
 // Geometry of the current call.
 struct Geometry {
-  int periodic;                         // 1: orthorhombic minimum image
+  int periodic;                         // 1: one orthorhombic box, minimum image, cell grid
   float box[3], inv_box[3];
   int nc[3];                            // cells per dimension (periodic)
   float cell_scale[3];                  // nc * (1/L) in FP32
   float cell_len[3];                    // L / nc in FP32
   int n_bins;                           // cells (periodic) or systems (batched)
+  // Batched calls with per-system boxes (periodic = 0, bins are systems):
+  // sys_box[2 s] = (L_x, L_y, L_z, 0) and sys_box[2 s + 1] = (1/L_x, 1/L_y,
+  // 1/L_z, 0) in FP32, zeros for an open system; sbin[slot] = system.  Null
+  // otherwise.
+  const float4* sys_box;
+  const int* sbin;
 };
+
+// Minimum-image lengths for the pairs of one centre atom: the call's box,
+// the box of the centre's system in a batch, or none (on = false).
+struct MinImage {
+  float L[3], iL[3];
+  bool on;
+};
+
+__device__ __forceinline__ MinImage min_image_of_system(const Geometry& g, int sys) {
+  MinImage b;
+  if (g.sys_box) {
+    const float4 lo = g.sys_box[2 * sys], hi = g.sys_box[2 * sys + 1];
+    b.L[0] = lo.x; b.L[1] = lo.y; b.L[2] = lo.z;
+    b.iL[0] = hi.x; b.iL[1] = hi.y; b.iL[2] = hi.z;
+    b.on = lo.x > 0.f;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b.L[k] = g.box[k];
+      b.iL[k] = g.inv_box[k];
+    }
+    b.on = g.periodic != 0;
+  }
+  return b;
+}
+
+__device__ __forceinline__ MinImage min_image_at(const Geometry& g, int slot) {
+  return min_image_of_system(g, g.sys_box ? g.sbin[slot] : 0);
+}
+
+// r^2 of d = pj - pi under the minimum image, every operation one IEEE FP32
+// operation in a fixed order (no contraction): the neighbour predicate of the
+// cell list and the pair lists.
+__device__ __forceinline__ float pair_r2_exact(const float4& pi, const float4& pj, const MinImage& b) {
+#pragma clang fp contract(off)
+  float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  if (b.on) {
+    float sx = rintf(dx * b.iL[0]);
+    float sy = rintf(dy * b.iL[1]);
+    float sz = rintf(dz * b.iL[2]);
+    float tx = sx * b.L[0], ty = sy * b.L[1], tz = sz * b.L[2];
+    dx = dx - tx; dy = dy - ty; dz = dz - tz;
+  }
+  float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+  float r2 = xx + yy;
+  return r2 + zz;
+}
 // Cells per dimension are capped so that a cell's coordinates pack into
 // 10 bits each (larger cells stay correct).
 constexpr int kMaxCellsPerDim = 1023;
@@ -192,6 +245,7 @@ struct Workspace {
   float* d_e = nullptr;
   float* d_mm_part = nullptr;  // MM channel per-workgroup partials [mm_partial_floats(max_atoms, max_mm)]
   float* d_q = nullptr;        // predicted atomic charges (member mean) [max_atoms], models with charges
+  float4* d_sys_box = nullptr; // [2 max_sys] per-system boxes of a batched call (Geometry::sys_box)
 };
 
 }  // namespace nnp
@@ -238,6 +292,7 @@ struct nnp_model : nnp::Workspace {
   int topo_n_atoms = -1;
   int topo_link_version = -1;
   std::vector<int> topo_Z, topo_idx, topo_offsets;
+  std::vector<float> topo_boxes;       // per-system boxes of the last batched call as uploaded ([n_sys][8])
   int n_nnp = 0;
 
   // graph replay of identical calls
@@ -246,7 +301,9 @@ struct nnp_model : nnp::Workspace {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uint8_t> graph_key;
-  int graph_replays = 0;
+  int64_t graph_replays = 0;           // launches of an unchanged graph
+  int64_t graph_updates = 0;           // graphs updated in place for a call with new arguments
+  int64_t graph_builds = 0;            // graphs instantiated
 
   // stage timing
   std::vector<hipEvent_t> prof_ev;   // [call][stage][2]

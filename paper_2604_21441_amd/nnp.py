@@ -182,10 +182,12 @@ def nnp_compute_pairs(h, pos: torch.Tensor, Z, box, nnp_idx, pairs: torch.Tensor
 
 
 def nnp_compute_batch(h, offsets, pos: torch.Tensor, Z, energies: torch.Tensor, forces: torch.Tensor,
-                      stream=None) -> None:
+                      boxes=None, stream=None) -> None:
+    """Packed systems; boxes: None (all open) or [n_sys, 3] lengths, a zero row for an open system."""
     Oa, Op = _host(offsets, np.int32, "offsets")
     Za, Zp = _host(Z, np.int32, "Z")
-    st = L.load().nnp_compute_batch(h, Oa.size - 1, Op, _dptr(pos, torch.float32, "pos"), Zp,
+    Ba, Bp = _host(None if boxes is None else np.asarray(boxes, np.float32).reshape(-1), np.float32, "boxes")
+    st = L.load().nnp_compute_batch(h, Oa.size - 1, Op, _dptr(pos, torch.float32, "pos"), Zp, Bp,
                                     _dptr(energies, torch.float64, "energies"),
                                     _dptr(forces, torch.float64, "forces"), _stream(stream))
     _check(st, "nnp_compute_batch")
@@ -332,8 +334,9 @@ class NNPModel:
         nnp_compute_pairs(self.h, pos, Z, box, nnp_idx, pairs, mm_pos, mm_q, E, F, Fmm, stream=stream)
         return E, F, Fmm
 
-    def compute_batch(self, pos: torch.Tensor, Z, offsets, out=None, stream=None):
-        """Per-system energies [n_sys] and forces [n, 3] (float64) of packed open systems."""
+    def compute_batch(self, pos: torch.Tensor, Z, offsets, boxes=None, out=None, stream=None):
+        """Per-system energies [n_sys] and forces [n, 3] (float64) of packed systems (boxes: None = all
+        open, or [n_sys, 3] box lengths with zero rows for open systems)."""
         offsets = np.asarray(offsets, dtype=np.int32)
         self._ensure(pos.shape[0], offsets.size - 1)
         if out is not None:
@@ -341,7 +344,7 @@ class NNPModel:
         else:
             E = torch.empty(offsets.size - 1, dtype=torch.float64, device=pos.device)
             F = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
-        nnp_compute_batch(self.h, offsets, pos, Z, E, F, stream=stream)
+        nnp_compute_batch(self.h, offsets, pos, Z, E, F, boxes=boxes, stream=stream)
         return E, F
 
     def set_graph(self, enable: bool) -> None:
@@ -365,6 +368,16 @@ class NNPModel:
     def read(self, which: int) -> np.ndarray:
         return nnp_read_buffer(self.h, which)
 
+    def _autograd_outputs(self, pos: torch.Tensor):
+        """Output buffers the autograd path reuses call after call (same size, same device)."""
+        key = (pos.shape[0], str(pos.device))
+        buf = getattr(self, "_ag_buf", None)
+        if buf is None or buf[0] != key:
+            E = torch.empty(1, dtype=torch.float64, device=pos.device)
+            F = torch.empty((pos.shape[0], 3), dtype=torch.float64, device=pos.device)
+            self._ag_buf = buf = (key, (E, F, None))
+        return buf[1]
+
     def energy(self, pos: torch.Tensor, Z=None, box=None, nnp_idx=None):
         """Differentiable E_ML(pos): backward gives -forces via the library's adjoint."""
         return NNPEnergy.apply(pos, self, Z, box, nnp_idx)
@@ -382,14 +395,20 @@ class NNPModel:
 
 
 class NNPEnergy(torch.autograd.Function):
-    """E = NNPEnergy.apply(pos, model, Z, box, nnp_idx); dE/dpos = -F from the same call."""
+    """E = NNPEnergy.apply(pos, model, Z, box, nnp_idx); dE/dpos = -F from the same call.
+
+    The library writes into the model's persistent output buffers (so repeated
+    calls replay one captured graph); the returned energy and the saved forces
+    are copies of them."""
 
     @staticmethod
     def forward(ctx, pos, model, Z, box, nnp_idx):
         p = pos.detach()
         if p.dtype != torch.float32:
             p = p.float()
-        E, F, _ = model.compute(p.contiguous(), Z, box, nnp_idx)
+        E, F, _ = model.compute(p.contiguous(), Z, box, nnp_idx, out=model._autograd_outputs(p))
+        E = E.clone()
+        F = F.clone()
         ctx.save_for_backward(F)
         ctx.in_dtype = pos.dtype
         return E[0].to(pos.dtype) if pos.dtype == torch.float64 else E[0]

@@ -34,6 +34,17 @@ def rel_rmse(F, Fref):
     return float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
 
 
+def worst_atom(F, Fref):
+    """Largest per-atom force error relative to the RMS atomic force of the reference: a
+    few badly wrong atoms cannot hide in a norm over many atoms (BF16 rounding gives a few
+    times the relative RMSE; one wrong atom is of order 1)."""
+    err = np.linalg.norm(F - Fref, axis=1)
+    return float(err.max() / np.sqrt(np.mean(np.sum(Fref ** 2, axis=1))))
+
+
+BF16_ATOM_BOUND = 0.15
+
+
 @pytest.fixture(scope="module")
 def P():
     return _lib()
@@ -57,7 +68,9 @@ def water_models(P, w_water):
 
 @pytest.fixture(scope="module")
 def boxes():
-    # "large" (18,432 atoms) adds a box of several scan chunks per species
+    # "large" (18,432 atoms, 10^3 cells x 2 species): a second periodic size on the
+    # fused one-chunk scan-and-scatter path; the multi-chunk scan (more than 16,384
+    # bins) is checked bit for bit in test_gpu_full_size.py
     c2 = sy.water_box(4096, 49.7, seed=0)
     # "c2s": the same box with every atom moved by whole box lengths (-3..3 per
     # component), so that positions lie far outside [0, L)
@@ -176,8 +189,9 @@ def test_energy_forces_bf16(P, water_models, boxes, oracle_res, name):
     E, F, _ = _run(water_models["bf16"], pos, Z, box)
     ref = oracle_res[name]
     n = len(Z)
-    assert abs(E[0] - ref["E"]) / n < 1e-2
+    assert abs(E[0] - ref["E"]) / n < 2e-3
     assert rel_rmse(F, ref["F"]) < 1e-2
+    assert worst_atom(F, ref["F"]) < BF16_ATOM_BOUND
 
 
 def test_forces_match_gpu_finite_differences(P, water_models, boxes):
@@ -329,8 +343,9 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
         assert abs(E[0] - ref["E"]) / n < 1e-6
         assert rel_rmse(F, ref["F"]) < 1e-5
     else:
-        assert abs(E[0] - ref["E"]) / n < 1e-2
+        assert abs(E[0] - ref["E"]) / n < 2e-3
         assert rel_rmse(F, ref["F"]) < 1e-2
+        assert worst_atom(F, ref["F"]) < BF16_ATOM_BOUND
     perm = m.read(P._lib.NNP_BUF_PERM)
     x = m.read(P._lib.NNP_BUF_DESCRIPTOR)[:, :128]
     xr = np.empty(x.shape)
@@ -816,31 +831,3 @@ def test_error_paths(P, w_water):
     P.nnp_compute(m.h, torch.from_numpy(bad).cuda(), Z, box, None, None, None, E, F)
     assert m.status() == P._lib.NNP_ENONFINITE
     m.close()
-
-
-# ------------------------------------------- full-size sampled parity (98k)
-@pytest.mark.parametrize("n_mol,L", [(32768, 99.4), (87000, 137.7)], ids=["98304_atoms", "261000_atoms"])
-def test_large_box_sampled_parity_fp32_bf16(P, water_models, w_water, n_mol, L):
-    """Full-size boxes in the benchmark's launch configuration: exact oracle forces and
-    atomic energies on 24 sampled atoms; BF16 against FP32 over every atom."""
-    pos, Z, box = sy.water_box(n_mol, L, seed=0)
-    res = {}
-    for prec in ("fp32", "bf16"):
-        E, F, _ = _run(water_models[prec], pos, Z, box)
-        perm = water_models[prec].read(P._lib.NNP_BUF_PERM)
-        e = np.empty(len(perm))
-        e[perm] = water_models[prec].read(P._lib.NNP_BUF_ATOM_ENERGY)
-        res[prec] = (E, F, e)
-    rng = np.random.default_rng(9)
-    sample = np.sort(rng.choice(len(Z), 24, replace=False))
-    I, J = orc.neighbour_pairs(pos, float(WATER["rc_rad"]), box, centres=sample)
-    cs = np.unique(np.concatenate([sample, J]))
-    ref = orc.evaluate(pos, Z, WATER, w_water, box=box, centres=cs)
-    e_ref = dict(zip(cs.tolist(), ref["e"]))
-    F32 = res["fp32"][1][sample]
-    assert rel_rmse(F32, ref["F"][sample]) < 1e-5
-    assert max(abs(res["fp32"][2][a] - e_ref[a]) for a in sample) < 2e-5
-    assert rel_rmse(res["bf16"][1][sample], ref["F"][sample]) < 1e-2
-    # BF16 against FP32 over all 98,304 atoms
-    assert rel_rmse(res["bf16"][1], res["fp32"][1]) < 1e-2
-    assert abs(res["bf16"][0][0] - res["fp32"][0][0]) / len(Z) < 1e-2
