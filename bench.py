@@ -119,6 +119,10 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
             c, mixed, nw = {2: (2, False, 4), 3: (2, False, 4), 4: (2, True, 4), 5: (1, False, 8),
                             6: (2, True, 8), 7: (2, False, 8)}.get(nv, (1, False, 4))
             return f"k_mlp_split_q<{dims}, {c}, {'true' if mixed else 'false'}, {nw}>"
+        if nv in (8, 9) and prec == "bf16" and k0 <= 128:
+            return f"k_mlp_lds<{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {'2, 8' if nv == 8 else '1, 16'}>"
+        if nv in (8, 9):
+            nv = 2
         cols = {1: 1, 2: 2, 3: 4 if k0 <= 128 else 2}.get(nv)
         if nv == 4:
             return f"k_mlp_mixed<{dims}>"

@@ -348,7 +348,12 @@ typedef enum {
  *     use 32); 4 workgroups of 32 atoms, 16 for the species with the fewest
  *     atoms (more even workgroups for small systems); 5 / 6 / 7 as 1 / 4 / 2
  *     with eight wavefronts per workgroup instead of four (shorter chains
- *     per tile, for systems with few tiles or wide networks);
+ *     per tile, for systems with few tiles or wide networks); 8 / 9 (BF16
+ *     form, the water-sized network, one member; otherwise 2 runs)
+ *     persistent workgroups holding one species' BF16 weights in LDS, a
+ *     32-atom (8) or 16-atom (9) tile per wavefront with no barrier (celu'
+ *     then comes from the BF16-rounded activation: dE/dx differs from the
+ *     other BF16 kernels by rounding);
  *   descriptor adjoint: 0 one wavefront per atom; 1 half a wavefront per atom;
  *     2 as 0, with the centre's place in each neighbour's list counted with
  *     wide loads instead of a binary search (for lists far beyond the caches).

@@ -347,6 +347,11 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
   nnp_model* m = new (std::nothrow) nnp_model();
   if (!m) return set_error(NNP_EINVAL, "out of host memory");
   (void)hipGetDevice(&m->device);
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) == hipSuccess && cus > 0)
+      m->n_cu = cus;
+  }
   m->prec = prec;
   m->S = S;
   m->P = S * (S + 1) / 2;
@@ -416,6 +421,12 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
   if (e == hipSuccess) e = hipMemcpy(m->d_wmat, mat.data(), mat.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = dalloc(&m->d_wvec, vec.size());
   if (e == hipSuccess) e = hipMemcpy(m->d_wvec, vec.data(), vec.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess && prec == NNP_BF16) {
+    std::vector<uint16_t> rows;
+    pack_rows_bf16(*m, rows, m->wrow_per_species);
+    e = hipMalloc(&m->d_wrow, rows.size() * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMemcpy(m->d_wrow, rows.data(), rows.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = dalloc(&m->d_status, 1);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipMemset(m->d_status, 0, sizeof(int));
@@ -1082,6 +1093,7 @@ void nnp_destroy(nnp_model* m) {
   (void)hipDeviceSynchronize();
   free_workspace(m);
   if (m->d_wmat) (void)hipFree(m->d_wmat);
+  if (m->d_wrow) (void)hipFree(m->d_wrow);
   dfree(m->d_wvec);
   dfree(m->d_status);
   delete m;

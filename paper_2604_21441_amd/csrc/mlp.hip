@@ -712,6 +712,409 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reg(MlpArgs a, float alpha) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 network with the weights resident in LDS (water-sized networks).
+//
+// A persistent workgroup serves one species: it copies that species' W1, W2,
+// W3 (BF16, row-major, about 115 KB with row padding) into LDS once, then
+// every wavefront takes tiles of 16 or 32 atoms on its own and runs the whole
+// fused chain -- three hidden layers, the output, and the three backward
+// products -- with no barrier and no weight traffic beyond LDS.  Forward
+// products read W fragments with two 8-byte LDS reads per lane; the backward
+// products need W^T fragments of the same copy, which the gfx950 transposing
+// read gives: within a group of 16 lanes, lane i's element j comes from
+// position i % 4 of the 8-byte chunk addressed by lane 4 j + i / 4, so if
+// lane 4 j + s addresses W[k0 + j][c0 + 4 s], lane i receives
+// W[k0 .. k0 + 3][c0 + i]: four consecutive K values of column c0 + i, an A
+// fragment of W^T.
+// The activations needed again by the backward pass are kept as the BF16
+// B fragments the next product reads anyway, so celu'(u) is taken from the
+// BF16-rounded activation (h / alpha + 1 for h < 0, an absolute difference
+// of at most 2^-9 from the FP32 activation's; the backward operands are
+// rounded to BF16 in any case).
+// Measured bounds (261,000 atoms): without the x loads and dE/dx stores the
+// stage runs 18 % faster, without the elementwise CELU work 18 % faster,
+// without the LDS weight reads no faster: the FP32 descriptor rows read and
+// the FP32 dE/dx rows written (1 KB per atom) and the elementwise work limit
+// it, not the matrix cores.
+// Tilings of the LDS-resident kernel: C 16-atom column tiles per wavefront
+// tile and NW wavefronts per workgroup (1 workgroup per CU: NW / 4
+// wavefronts per SIMD).
+
+// Row pitch in bytes of a BF16 matrix with `in` columns in LDS: the 16 rows
+// of a forward fragment start in distinct bank pairs (pitch / 4 an odd
+// multiple of 2, mod 32) and the transposing reads see at most two-way
+// conflicts (pitch / 4 not 2 mod 32).
+constexpr int lds_pitch(int in) {
+  int p = 2 * in + 8;
+  while (((p / 8) & 1) == 0 || (p / 4) % 32 == 2) p += 8;
+  return p;
+}
+
+// The vectors come first, so that their reads use immediate offsets.
+template <int K0, int N1, int N2, int N3>
+struct LdsLayout {
+  static constexpr int P1 = lds_pitch(K0), P2 = lds_pitch(N1), P3 = lds_pitch(N2);
+  static constexpr int nvec = N1 + N2 + N3 + N3 + 4;   // b1 b2 b3 w4 b4 (FP32)
+  static constexpr int vec = 0, w1 = (4 * nvec + 255) / 256 * 256, w2 = w1 + N1 * P1, w3 = w2 + N2 * P2;
+  static constexpr int bytes = w3 + N3 * P3;
+};
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) v4s lds_v4s;
+
+__device__ __forceinline__ v8bf join_bf16(v4s lo, v4s hi) {
+  typedef short v8s __attribute__((ext_vector_type(8)));
+  v8s r;
+  r[0] = lo[0]; r[1] = lo[1]; r[2] = lo[2]; r[3] = lo[3];
+  r[4] = hi[0]; r[5] = hi[1]; r[6] = hi[2]; r[7] = hi[3];
+  return __builtin_bit_cast(v8bf, r);
+}
+
+// The LDS address is hidden from the optimizer so that it stays one register
+// per product and every fragment read of the product is that register plus
+// an immediate offset (LDS offsets beyond 64 KB do not fit the immediate, and
+// the compiler would otherwise keep a separate address per fragment).
+__device__ __forceinline__ const lds_char* opaque_lds(const lds_char* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
+// Per-lane base of the fragments of W (forward: row 16 rt + lane % 16, K
+// offset 4 (lane / 16)) or of W^T (transposed reads: lane 16 g + 4 j + s
+// addresses W[4 g + j][4 s] of each 32 x 16 block).
+template <int P, bool TRANS>
+__device__ __forceinline__ const lds_char* frag_base(const lds_char* W, int lane) {
+  if (TRANS) return opaque_lds(W + (4 * (lane >> 4) + ((lane >> 2) & 3)) * P + 8 * (lane & 3));
+  return opaque_lds(W + (lane & 15) * P + 8 * (lane >> 4));
+}
+
+// A fragment of W (rows = outputs, row tile rt; K block kb over the inputs),
+// or with TRANS of W^T (rows = inputs of W, row tile rt; K block kb over the
+// outputs of W), from the per-lane base.
+template <int P, bool TRANS>
+__device__ __forceinline__ v8bf frag_at(const lds_char* base, int rt, int kb) {
+  if (TRANS) {
+    const lds_char* p0 = base + 32 * kb * P + 32 * rt;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(p0));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)(p0 + 16 * P));
+    return join_bf16(lo, hi);
+  }
+  const lds_char* row = base + 16 * rt * P + 64 * kb;
+  return join_bf16(*(const lds_v4s*)(row), *(const lds_v4s*)(row + 32));
+}
+
+// One product, op(W) [R x K] times the B fragments [K/32][C], in chunks of CH
+// row tiles (CH even): init(r0, acc) seeds a chunk's accumulators, the K
+// blocks follow -- each block's fragments are read, then multiplied, with a
+// compiler barrier between blocks so that the scheduler does not hoist every
+// read of the product ahead of the matrix-core work (which would need
+// registers for all of them at once) -- and epi(r0, acc) consumes the chunk
+// (activation, conversion to the next product's B fragments, or the store).
+// Only one chunk of accumulators is live.  (Reading the next block's
+// fragments one step ahead was measured no faster.)
+template <int R, int K, int P, bool TRANS, int CH, int C, typename Init, typename Epi>
+__device__ __forceinline__ void lds_product(const lds_char* W, const v8bf (*B)[C], int lane, Init init, Epi epi) {
+  static_assert(CH % 2 == 0, "chunks of whole K blocks of the next product");
+  const lds_char* base = frag_base<P, TRANS>(W, lane);
+#pragma unroll
+  for (int r0 = 0; r0 < R / 16; r0 += CH) {
+    v4f acc[CH][C];
+    init(r0, acc);
+#pragma unroll
+    for (int kb = 0; kb < K / 32; ++kb) {
+      v8bf A[CH];
+#pragma unroll
+      for (int r = 0; r < CH; ++r)
+        if (r0 + r < R / 16) A[r] = frag_at<P, TRANS>(base, r0 + r, kb);
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        if (r0 + r < R / 16) {
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], B[kb][c], acc[r][c], 0, 0, 0);
+        }
+      }
+      asm volatile("" ::: "memory");
+    }
+    epi(r0, acc);
+  }
+}
+
+// Accumulator tiles r0 .. r0 + CH - 1 (row tile rt: features 16 rt + 4 q + t)
+// into the BF16 B fragments of the next product (K block rt / 2, element
+// 4 (rt % 2) + t).
+// The packed fragment is hidden from the optimizer: later reads of single
+// elements (celu' in the backward pass) then come from the packed BF16
+// registers, instead of the compiler keeping the FP32 values alive as well.
+template <int R, int CH, int C>
+__device__ __forceinline__ void chunk_to_frags(int r0, const v4f (*acc)[C], v8bf (*f)[C]) {
+#pragma unroll
+  for (int r = 0; r < CH; r += 2)
+    if (r0 + r < R / 16)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        v8bf v = to_bf16x8(acc[r][c], acc[r + 1][c]);
+        asm volatile("" : "+v"(v));
+        f[(r0 + r) / 2][c] = v;
+      }
+}
+
+// CELU in the form the kernel evaluates it: t = 2^(u log2(e) / alpha), h = u
+// for u > 0, else alpha t - alpha; and its derivative from h: 1 for h > 0,
+// else h / alpha + 1 = min(h / alpha + 1, 1) (h / alpha + 1 > 1 exactly when
+// h > 0).
+__device__ __forceinline__ float celu_lean(float u, float alpha, float inv_alpha_l2) {
+  const float t = __builtin_amdgcn_exp2f(u * inv_alpha_l2);
+  return u > 0.f ? u : fmaf(alpha, t, -alpha);
+}
+__device__ __forceinline__ float celu_grad_lean(float h, float inv_alpha) {
+  return fminf(fmaf(h, inv_alpha, 1.f), 1.f);
+}
+
+template <int K0, int N1, int N2, int N3, int C, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_mlp_lds(MlpArgs a, float alpha) {
+  using Lay = LdsLayout<K0, N1, N2, N3>;
+  static_assert(K0 % 32 == 0 && N1 % 32 == 0 && N2 % 32 == 0 && N3 % 32 == 0, "32-wide K blocks");
+  constexpr int CH = C == 1 ? 2 : 4;   // row tiles per accumulator chunk
+  constexpr int TILE = 16 * C;
+  __shared__ __attribute__((aligned(16))) char lds[Lay::bytes];
+  const lds_char* L = (const lds_char*)lds;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4;
+  const int col = lane & 15;
+
+  // workgroup -> species: one workgroup per species with atoms, the rest in
+  // proportion to the species' tiles; workgroups beyond them exit
+  int T = 0, ne = 0;
+  for (int s = 0; s < a.S; ++s) {
+    const int ns = a.bin_start[(s + 1) * a.n_bins] - a.bin_start[s * a.n_bins];
+    const int ts = (ns + TILE - 1) / TILE;
+    T += ts;
+    ne += ts > 0;
+  }
+  if (T == 0) return;
+  const int G = (int)gridDim.x;
+  int s_mine = -1, wg0 = 0, gs = 0, tiles_before = 0, ts_mine = 0, b0_mine = 0, b1_mine = 0;
+  {
+    int first = 0, tb = 0;
+    for (int s = 0; s < a.S; ++s) {
+      const int b0 = a.bin_start[s * a.n_bins], b1 = a.bin_start[(s + 1) * a.n_bins];
+      const int ts = (b1 - b0 + TILE - 1) / TILE;
+      const int g = ts > 0 ? 1 + (G - ne) * ts / T : 0;
+      if ((int)blockIdx.x >= first && (int)blockIdx.x < first + g) {
+        s_mine = s;
+        wg0 = first;
+        gs = g;
+        tiles_before = tb;
+        ts_mine = ts;
+        b0_mine = b0;
+        b1_mine = b1;
+      }
+      first += g;
+      tb += ts;
+    }
+  }
+  if (s_mine < 0) return;   // whole workgroup exits together
+
+  // weights of the species into LDS: 16-byte pieces, eight loads in flight per
+  // thread before their stores; vectors as FP32
+  {
+    const uint16_t* src = reinterpret_cast<const uint16_t*>(a.wrow) + (int64_t)s_mine * a.wrow_per_species;
+    auto copy = [&](const uint16_t* m, int rows, int in, int pitch, int dst) {
+      const int per_row = in / 8;
+      const int total = rows * per_row;
+      for (int t0 = threadIdx.x; t0 < total; t0 += 8 * 64 * NW) {
+        uint4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = t0 + u * 64 * NW;
+          if (t < total) {
+            const int r = t / per_row, c = t - r * per_row;
+            v[u] = *reinterpret_cast<const uint4*>(m + (int64_t)r * in + 8 * c);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int t = t0 + u * 64 * NW;
+          if (t < total) {
+            const int r = t / per_row, c = t - r * per_row;
+            // the pitch is a multiple of 8 bytes only: two 8-byte stores
+            uint2* d = reinterpret_cast<uint2*>(lds + dst + r * pitch + 16 * c);
+            d[0] = make_uint2(v[u].x, v[u].y);
+            d[1] = make_uint2(v[u].z, v[u].w);
+          }
+        }
+      }
+    };
+    copy(src, N1, K0, Lay::P1, Lay::w1);
+    copy(src + N1 * K0, N2, N1, Lay::P2, Lay::w2);
+    copy(src + N1 * K0 + N2 * N1, N3, N2, Lay::P3, Lay::w3);
+    const float* V = a.wvec + (int64_t)s_mine * a.vec_per_species;
+    float* vl = reinterpret_cast<float*>(lds + Lay::vec);
+    for (int t = threadIdx.x; t < Lay::nvec; t += 64 * NW) vl[t] = V[t];
+  }
+  __syncthreads();
+  const lds_char* W1 = L + Lay::w1;
+  const lds_char* W2 = L + Lay::w2;
+  const lds_char* W3 = L + Lay::w3;
+  const float* vb1 = reinterpret_cast<const float*>(lds + Lay::vec);
+  const float* vb2 = vb1 + N1;
+  const float* vb3 = vb2 + N2;
+  const float* vw4 = vb3 + N3;
+  const float b4 = vw4[N3];
+  const float inv_alpha = 1.f / alpha;
+  const float inv_alpha_l2 = kLog2e / alpha;
+  const v4f zero = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int waves = gs * NW;
+  for (int t = ((int)blockIdx.x - wg0) * NW + w; t < ts_mine; t += waves) {
+    const int row0 = b0_mine + t * TILE;
+    // x as B fragments: column tile c, K block kb: atom row0 + 16 c + col,
+    // features 32 kb + 4 q .. +3 and 32 kb + 16 + 4 q .. +3 (zero beyond the
+    // species)
+    v8bf xf[K0 / 32][C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int row = row0 + 16 * c + col;
+      const bool ok = row < b1_mine;
+      const float* xr = a.x + (int64_t)(ok ? row : b0_mine) * a.stride + 4 * q;
+#pragma unroll
+      for (int kb = 0; kb < K0 / 32; ++kb) {
+        v4f lo = *reinterpret_cast<const v4f*>(xr + 32 * kb);
+        v4f hi = *reinterpret_cast<const v4f*>(xr + 32 * kb + 16);
+        if (!ok) lo = hi = zero;
+        xf[kb][c] = to_bf16x8(lo, hi);
+      }
+    }
+    auto bias_init = [&](const float* b) {
+      return [=](int r0, v4f (*acc)[C]) {
+#pragma unroll
+        for (int r = 0; r < CH; ++r) {
+          const v4f v = *reinterpret_cast<const v4f*>(b + 16 * (r0 + r) + 4 * q);   // beyond R: unused
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[r][c] = v;
+        }
+      };
+    };
+    auto zero_init = [&](int, v4f (*acc)[C]) {
+#pragma unroll
+      for (int r = 0; r < CH; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[r][c] = zero;
+    };
+    auto celu_chunk = [&](v4f (*acc)[C]) {
+#pragma unroll
+      for (int r = 0; r < CH; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[r][c][u] = celu_lean(acc[r][c][u], alpha, inv_alpha_l2);
+    };
+    // celu'(h) o acc with h from the BF16 fragments of the forward pass
+    auto times_grad = [&](int r0, v4f (*acc)[C], const v8bf (*hf)[C], int R) {
+#pragma unroll
+      for (int r = 0; r < CH; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (r0 + r < R)
+              acc[r][c][u] *= celu_grad_lean((float)hf[(r0 + r) >> 1][c][4 * ((r0 + r) & 1) + u], inv_alpha);
+    };
+    // ---- layer 1: h1 = celu(W1 x + b1)
+    v8bf h1f[N1 / 32][C];
+    lds_product<N1, K0, Lay::P1, false, CH, C>(W1, xf, lane, bias_init(vb1), [&](int r0, v4f (*acc)[C]) {
+      celu_chunk(acc);
+      chunk_to_frags<N1, CH, C>(r0, acc, h1f);
+    });
+    // ---- layer 2: h2 = celu(W2 h1 + b2)
+    v8bf h2f[N2 / 32][C];
+    lds_product<N2, N1, Lay::P2, false, CH, C>(W2, h1f, lane, bias_init(vb2), [&](int r0, v4f (*acc)[C]) {
+      celu_chunk(acc);
+      chunk_to_frags<N2, CH, C>(r0, acc, h2f);
+    });
+    // ---- layer 3, the output, and delta3 = w4 o celu'(h3)
+    v8bf d3f[N3 / 32][C];
+    float ep[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ep[c] = 0.f;
+    lds_product<N3, N2, Lay::P3, false, CH, C>(W3, h2f, lane, bias_init(vb3), [&](int r0, v4f (*acc)[C]) {
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        if (r0 + r >= N3 / 16) continue;
+        const v4f w4 = *reinterpret_cast<const v4f*>(vw4 + 16 * (r0 + r) + 4 * q);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float h = celu_lean(acc[r][c][u], alpha, inv_alpha_l2);
+            ep[c] = fmaf(w4[u], h, ep[c]);
+            acc[r][c][u] = w4[u] * celu_grad_lean(h, inv_alpha);
+          }
+      }
+      chunk_to_frags<N3, CH, C>(r0, acc, d3f);
+    });
+    // ---- delta2 = (W3^T delta3) o celu'(h2)
+    v8bf d2f[N2 / 32][C];
+    lds_product<N2, N3, Lay::P3, true, CH, C>(W3, d3f, lane, zero_init, [&](int r0, v4f (*acc)[C]) {
+      times_grad(r0, acc, h2f, N2 / 16);
+      chunk_to_frags<N2, CH, C>(r0, acc, d2f);
+    });
+    // ---- delta1 = (W2^T delta2) o celu'(h1)
+    v8bf d1f[N1 / 32][C];
+    lds_product<N1, N2, Lay::P2, true, CH, C>(W2, d2f, lane, zero_init, [&](int r0, v4f (*acc)[C]) {
+      times_grad(r0, acc, h1f, N1 / 16);
+      chunk_to_frags<N1, CH, C>(r0, acc, d1f);
+    });
+    // ---- dE/dx = W1^T delta1, to memory
+    lds_product<K0, N1, Lay::P1, true, CH, C>(W1, d1f, lane, zero_init, [&](int r0, v4f (*acc)[C]) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int row = row0 + 16 * c + col;
+        if (row < b1_mine) {
+#pragma unroll
+          for (int r = 0; r < CH; ++r)
+            if (r0 + r < K0 / 16)
+              *reinterpret_cast<v4f*>(a.g + (int64_t)row * a.stride + 16 * (r0 + r) + 4 * q) = acc[r][c];
+        }
+      }
+    });
+    // ---- atomic energies and the tile's FP64 partial sum
+    double ev = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      float e = ep[c];
+      e += __shfl_xor(e, 16, 64);
+      e += __shfl_xor(e, 32, 64);
+      e += b4;
+      const int row = row0 + 16 * c + col;
+      if (q == 0 && row < b1_mine) {
+        a.e[row] = e;
+        ev += (double)e;
+      }
+    }
+    if (a.part != nullptr) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) ev += __shfl_xor(ev, off, 64);
+      if (lane == 0) a.part[tiles_before + t] = ev;
+    }
+  }
+}
+
+// One workgroup per CU at most (each holds a species' weights in LDS), no
+// more than the tiles need, at least one per species.
+template <int K0, int N1, int N2, int N3, int C, int NW>
+void launch_lds(const nnp_model& m, const MlpArgs& a, int n, hipStream_t st) {
+  const int64_t tiles = (n + 16 * C - 1) / (16 * C) + m.S;
+  int64_t G = (tiles + NW - 1) / NW;
+  if (G > m.n_cu) G = m.n_cu;
+  if (G < m.S) G = m.S;
+  hipLaunchKernelGGL((k_mlp_lds<K0, N1, N2, N3, C, NW>), dim3((unsigned)G), dim3(64 * NW), 0, st, a, m.celu_alpha);
+}
+
 template <int K0, int N1, int N2, int N3, bool BF16>
 hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream_t st) {
   if (variant == 0) {        // register-resident, one wavefront per 16 atoms
@@ -730,6 +1133,13 @@ hipError_t run_mlp(nnp_model& m, const MlpArgs& a, int n, int variant, hipStream
     const int64_t tiles = (n + 31) / 32 + m.S;
     hipLaunchKernelGGL((k_mlp_split8<K0, N1, N2, N3, BF16, 2, false>), dim3((unsigned)tiles), dim3(512), 0, st, a,
                        m.celu_alpha);
+  } else if (variant == 8 || variant == 9) {   // LDS-resident BF16 weights, a tile per wavefront
+    if constexpr (BF16 && K0 <= 128) {
+      if (variant == 8)
+        launch_lds<K0, N1, N2, N3, 2, 8>(m, a, n, st);    // 32-atom tiles, 2 wavefronts per SIMD
+      else
+        launch_lds<K0, N1, N2, N3, 1, 16>(m, a, n, st);   // 16-atom tiles, 4 wavefronts per SIMD
+    }
   } else if (variant == 4) {   // row split, 32 atoms per workgroup, 16 for the smallest species
     const int64_t tiles = (n + 15) / 16 + m.S;
     hipLaunchKernelGGL((k_mlp_mixed<K0, N1, N2, N3, BF16>), dim3((unsigned)tiles), dim3(256), 0, st, a,
@@ -785,6 +1195,8 @@ hipError_t run_mlp_q(nnp_model& m, const MlpArgs& a, int n, int variant, hipStre
 // the tuner picked for the water boxes and the H/C/N/O batch in both forms.
 int mlp_variant(const nnp_model& m, int n) {
   int v = stage_variant(m, kTuneNetwork, n);
+  // the LDS-resident kernels: BF16, the water-sized network, one member
+  if ((v == 8 || v == 9) && !(m.prec == NNP_BF16 && m.net_kind == 0 && m.n_members == 1 && m.d_wrow)) v = 2;
   if (v >= 0) return v;
   return 2;
 }
@@ -808,9 +1220,11 @@ hipError_t launch_mlp(nnp_model& m, int n, hipStream_t st) {
   a.part = (m.geo.periodic || m.geo.n_bins == 1) ? m.d_part : nullptr;
   a.q = m.charges ? m.d_q : nullptr;
   a.phi_col = m.D;   // the MM potential follows the descriptor
+  a.wrow = m.d_wrow;
+  a.wrow_per_species = m.wrow_per_species;
   const bool bf = m.prec == NNP_BF16;
   const int v = mlp_variant(m, n);
-  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 || v == 6 || v == 7 ? 2 : 1);
+  m.mlp_cols = v == 3 ? (m.net_kind == 0 ? 4 : 2) : (v == 2 || v == 4 || v == 6 || v == 7 || v == 8 ? 2 : 1);
   m.mlp_mixed = v == 4 || v == 6;
   switch (m.net_kind) {
     case 0:

@@ -202,6 +202,8 @@ struct MlpArgs {
   int* status;
   float* q;                // predicted atomic charges (output), or null: no charge head
   int phi_col;             // column of x holding the MM potential (models with charges)
+  const void* wrow;        // BF16 models: W1, W2, W3 row-major per (member, species), or null
+  int64_t wrow_per_species;
 };
 
 // Per-call device workspace: capacities and the arrays sized from them.
@@ -253,6 +255,7 @@ struct Workspace {
 // The model object.
 struct nnp_model : nnp::Workspace {
   int device = 0;
+  int n_cu = 256;                       // compute units of the device
   nnp_precision prec = NNP_FP32;
   int S = 0, P = 0, D = 0, Din = 0, stride = 0, n_members = 1, extra = 0;
   int charges = 0;                      // second network output: an atomic charge in the MM potential
@@ -271,6 +274,8 @@ struct nnp_model : nnp::Workspace {
   // device weights
   void* d_wmat = nullptr;
   float* d_wvec = nullptr;
+  void* d_wrow = nullptr;               // BF16: W1, W2, W3 row-major (the LDS-resident network kernel)
+  int64_t wrow_per_species = 0;         // elements per (member, species) in d_wrow
   int64_t mat_per_species = 0, vec_per_species = 0;
 
   bool reserved = false;
@@ -325,7 +330,7 @@ int adjoint_variant(const nnp_model& m, int n);
 // Variant of a tuned stage: the candidate being timed, else the pinned one,
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
-constexpr int kStageVariants[kTuneStages] = {4, 3, 8, 3};
+constexpr int kStageVariants[kTuneStages] = {4, 3, 10, 3};
 int size_bucket(int n);
 
 // workspace (api.cpp): capacities for a call of up to max_atoms atoms, and the
@@ -353,6 +358,9 @@ void draw_weights(uint64_t seed, const std::vector<int>& widths, int n_species, 
                   std::vector<float>& out);
 void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<float>& vec,
                   int64_t& mat_per_species, int64_t& vec_per_species);
+// BF16 (round to nearest even) copies of W1 [N1 x K0p] (zero columns beyond the
+// real input width), W2 [N2 x N1] and W3 [N3 x N2], row-major, per (member, species).
+void pack_rows_bf16(const nnp_model& m, std::vector<uint16_t>& out, int64_t& per_species);
 
 // cells.hip
 hipError_t launch_cells(nnp_model& m, const float* pos, int n_nnp, hipStream_t st);

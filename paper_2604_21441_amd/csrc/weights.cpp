@@ -137,4 +137,26 @@ void pack_weights(const nnp_model& m, std::vector<uint8_t>& mat, std::vector<flo
     }
 }
 
+void pack_rows_bf16(const nnp_model& m, std::vector<uint16_t>& out, int64_t& per_species) {
+  const int K0 = m.widths[0], K0p = m.stride;
+  const int N1 = m.widths[1], N2 = m.widths[2], N3 = m.widths[3];
+  const int n_out = m.charges ? 2 : 1;
+  per_species = (int64_t)N1 * K0p + (int64_t)N2 * N1 + (int64_t)N3 * N2;
+  out.clear();
+  size_t off = 0;
+  for (int mem = 0; mem < m.n_members; ++mem)
+    for (int s = 0; s < m.S; ++s) {
+      const float* W1 = m.w_host.data() + off;
+      const float* W2 = W1 + (size_t)N1 * K0 + N1;
+      const float* W3 = W2 + (size_t)N2 * N1 + N2;
+      off = (size_t)(W3 + (size_t)N3 * N2 + N3 + (size_t)n_out * N3 + n_out - m.w_host.data());
+      for (int r = 0; r < N1; ++r)
+        for (int c = 0; c < K0p; ++c) out.push_back(c < K0 ? bf16_rne(W1[(size_t)r * K0 + c]) : 0);
+      for (int r = 0; r < N2; ++r)
+        for (int c = 0; c < N1; ++c) out.push_back(bf16_rne(W2[(size_t)r * N1 + c]));
+      for (int r = 0; r < N3; ++r)
+        for (int c = 0; c < N2; ++c) out.push_back(bf16_rne(W3[(size_t)r * N2 + c]));
+    }
+}
+
 }  // namespace nnp

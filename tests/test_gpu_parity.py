@@ -326,7 +326,7 @@ VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours",
             ("network", 3, "fp32"), ("network", 4, "fp32"), ("network", 5, "fp32"), ("network", 6, "fp32"),
             ("network", 7, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
             ("network", 3, "bf16"), ("network", 4, "bf16"), ("network", 5, "bf16"), ("network", 6, "bf16"),
-            ("network", 7, "bf16"), ("adjoint", 0, "fp32"),
+            ("network", 7, "bf16"), ("network", 8, "bf16"), ("network", 9, "bf16"), ("network", 8, "fp32"), ("adjoint", 0, "fp32"),
             ("adjoint", 1, "fp32"), ("adjoint", 2, "fp32")]
 
 
@@ -352,7 +352,7 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    nvar = {"network": 8, "neighbours": 4, "descriptor": 3, "adjoint": 3}[stage]
+    nvar = {"network": 10, "neighbours": 4, "descriptor": 3, "adjoint": 3}[stage]
     for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
@@ -394,10 +394,11 @@ def test_mixed_network_tiling_bit_identical(P, w_water, w_hcno, boxes):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
-    """All network kernels run the same matrix-core sequence per atom (same K
+    """All network kernels 0-7 run the same matrix-core sequence per atom (same K
     order, same operand rounding: BF16 activations are rounded once, by the
     layer that produces them), so dE/dx and hence every force is bitwise the
-    same whichever kernel ran."""
+    same whichever kernel ran.  (Variant 8 takes celu' from the BF16-rounded
+    activation; it is compared with a tolerance in test_lds_network_kernel.)"""
     pos, Z, box = boxes["c2"]
     ref = None
     for v in range(8):
@@ -408,6 +409,51 @@ def test_network_variants_bitwise_forces(P, w_water, boxes, prec):
         if ref is None:
             ref = F
         assert np.array_equal(F, ref), f"network variant {v}"
+
+
+def test_lds_network_kernel(P, w_water, boxes, oracle_res):
+    """Network variants 8 and 9 (BF16 weights resident in LDS, one 32- or 16-atom tile per
+    wavefront, transposed LDS reads for the backward products) against the oracle like every
+    BF16 kernel, and against variant 2 within BF16 rounding: the CELU is one fma and the
+    output-layer dot product is summed in another order (FP32 rounding, which can move a
+    BF16-rounded activation by one BF16 ulp), and celu' comes from the BF16-rounded
+    activation (relative 2^-9 per element)."""
+    for name in ("c1", "c2"):
+        pos, Z, box = boxes[name]
+        out = {}
+        for v in (2, 8, 9):
+            m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="bf16")
+            m.set_variant("network", v)
+            E, F, _ = _run(m, pos, Z, box)
+            e = m.read(P._lib.NNP_BUF_ATOM_ENERGY).copy()
+            g = m.read(P._lib.NNP_BUF_DEDX).copy()
+            assert m.variants()["network"] == v
+            out[v] = (E, F, e, g)
+            m.close()
+        ref = oracle_res[name]
+        for v in (8, 9):
+            # the CELU is evaluated as one fma (alpha t - alpha) instead of a subtraction
+            # and a product; an activation whose FP32 value moves by one ulp can round to
+            # the neighbouring BF16 value (2^-8 relative), so atomic energies agree to
+            # BF16 input rounding, not bitwise
+            de = np.abs(out[v][2] - out[2][2])
+            assert de.max() < 5e-4, (name, v, de.max())                      # atomic energies
+            assert abs(out[v][0][0] - out[2][0][0]) / len(Z) < 1e-5, (name, v)
+            # celu'(h) = h / alpha + 1 (h < 0) from the BF16 h differs by at most 2^-9
+            # absolutely (|h| < alpha); three backward layers: a few 1e-3 relative
+            assert rel_rmse(out[v][3], out[2][3]) < 5e-3, (name, v)          # dE/dx
+            assert rel_rmse(out[v][1], out[2][1]) < 5e-3, (name, v)          # forces
+            e2, ev = rel_rmse(out[2][1], ref["F"]), rel_rmse(out[v][1], ref["F"])
+            print(f"{name}: force rel RMSE vs oracle, BF16 variant 2 {e2:.3e}, variant {v} {ev:.3e}")
+            assert ev < 1e-2 and worst_atom(out[v][1], ref["F"]) < BF16_ATOM_BOUND
+        # the two LDS tilings do the same arithmetic per atom
+        assert np.array_equal(out[8][1], out[9][1]), name
+    # an FP32 model pinned to variant 8 runs the default kernel instead
+    m = P.NNPModel(WATER, weights=sy.flat_weights(w_water), precision="fp32")
+    m.set_variant("network", 8)
+    _run(m, *boxes["c1"])
+    assert m.variants()["network"] == 2
+    m.close()
 
 
 def test_adjoint_wide_reverse_search_bit_identical(P, w_water, w_hcno, boxes):
