@@ -43,6 +43,9 @@ WORKLOADS = {
     "c3": dict(kind="water", n_mol=32768, L=99.4, desc="periodic water box, 32,768 molecules (98,304 atoms), L=99.4 A"),
     "c5a": dict(kind="water", n_mol=87000, L=137.7,
                 desc="periodic water box, 87,000 molecules (261,000 atoms), L=137.7 A"),
+    "c2e8": dict(kind="water", n_mol=4096, L=49.7, n_members=8,
+                 desc="periodic water box, 4,096 molecules (12,288 atoms), L=49.7 A, 8-member ensemble of "
+                      "networks sharing one descriptor (energy and forces are the member means)"),
     "c4": dict(kind="batch", n_sys=256, desc="256 open H/C/N/O walk molecules of 24-300 atoms, one batched call"),
     "c5b": dict(kind="solute_mm",
                 desc="60-atom H/C/N/O walk solute in 10,000 fixed-charge MM waters (30,000 point charges "
@@ -75,6 +78,7 @@ OPS_MM_BWD_PAIR = 80
 
 # rocprofv3 summaries committed under profiles/ (written by --summarize-profiles).
 PROFILE_TAGS = {"c1": "water192", "c2": "water12288", "c3": "water98304", "c5a": "water261000",
+                "c2e8": "water12288_ensemble8",
                 "c4": "hcno_batch256", "c5b": "hcno60_mm30000", "c5e": "hcno60_mm30000_charges"}
 CSRC = os.path.join(ROOT, "paper_2604_21441_amd", "csrc")
 CALIB_BYTES = 1 << 30   # --calib-copy: one device copy of this many bytes (read + write)
@@ -270,7 +274,8 @@ def build_inputs(name):
     if w["kind"] == "water":
         cfg = sy.model_config("water")
         pos, Z, box = sy.water_box(w["n_mol"], w["L"], seed=0)
-        return cfg, dict(pos=pos, Z=Z, box=box, offsets=None, mm_pos=None, mm_q=None)
+        return cfg, dict(pos=pos, Z=Z, box=box, offsets=None, mm_pos=None, mm_q=None,
+                         n_members=w.get("n_members", 1))
     if w["kind"] in ("solute_mm", "solute_ee"):
         cfg = sy.model_config("hcno_mm" if w["kind"] == "solute_mm" else "hcno_ee")
         s = sy.solute_in_water(seed=0)
@@ -285,7 +290,7 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
     reused), then the same number of calls with per-stage HIP-event timing."""
     import numpy as np
     import torch
-    m = P.NNPModel(cfg, weights=flat, precision=prec)
+    m = P.NNPModel(cfg, weights=flat, precision=prec, n_members=inp.get("n_members", 1))
     d = torch.from_numpy(inp["pos"]).cuda()
     n = d.shape[0]
     batched = inp["offsets"] is not None
@@ -362,6 +367,7 @@ def run_form(P, cfg, flat, inp, prec, steps, warmup, autotune=True):
         "n": n,
         "n_mm": 0 if inp.get("mm_pos") is None else len(inp["mm_q"]),
         "tuned": tuned,
+        "n_members": inp.get("n_members", 1),
     }
     m.close()
     return out
@@ -455,7 +461,7 @@ def _roofline(res, cfg, prec, stage, workload, periodic):
     t = res["stage_ms"][stage] * 1e-3
     D = widths[0]
     if stage == "network":
-        flops = network_flops_per_atom(widths) * n
+        flops = network_flops_per_atom(widths) * n * res.get("n_members", 1)
         ach = flops / t / 1e12
         return {"kernel": kernel, "bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_TFLOPS[prec],
                 "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_TFLOPS[prec], "traffic": traffic,
@@ -533,7 +539,7 @@ def main(argv=None):
 
     torch.set_num_threads(len(os.sched_getaffinity(0)))
     cfg, inp = build_inputs(args.workload)
-    w = sy.model_weights(cfg, seed=1)
+    w = sy.model_weights(cfg, seed=1, n_members=inp.get("n_members", 1))
     flat = sy.flat_weights(w)
     widths = list(cfg["widths"])
     n = len(inp["Z"])
@@ -592,8 +598,7 @@ def main(argv=None):
         from paper_2604_21441_amd.md import run_nve
         c2 = WORKLOADS["c2"]
         wcfg = sy.model_config("water")
-        wflat = flat if cfg is wcfg or list(cfg["widths"]) == list(wcfg["widths"]) else \
-            sy.flat_weights(sy.model_weights(wcfg, seed=1))
+        wflat = sy.flat_weights(sy.model_weights(wcfg, seed=1))
         pos2, Z2, box2 = sy.water_box(c2["n_mol"], c2["L"], seed=0)
         masses = np.array([sy.WATER_MASS[int(z)] for z in Z2])
         v0 = sy.maxwell_boltzmann(Z2, 300.0, seed=2)
@@ -628,7 +633,8 @@ def main(argv=None):
         "dtype": args.form,
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload]["desc"] + f", {args.form.upper()} form",
-                   "atoms": n, "form": args.form, "seeds": {"geometry": 0, "weights": 1}},
+                   "atoms": n, "form": args.form, "n_members": inp.get("n_members", 1),
+                   "seeds": {"geometry": 0, "weights": 1}},
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": report_forms,

@@ -563,17 +563,25 @@ def test_neighbour_sets_batched_and_open(P, w_hcno):
     m.close()
 
 
-def test_ensemble_members_average(P):
-    """An ensemble of networks sharing one descriptor: E and F are the member means."""
-    pos, Z, box = sy.water_box(64, 12.42, seed=0)
-    w2 = sy.model_weights(WATER, seed=1, n_members=3)
-    ref = orc.evaluate(pos, Z, WATER, w2, box=box)
+@pytest.mark.parametrize("n_mem,name", [(3, "c1"), (8, "c1"), (8, "c2")])
+def test_ensemble_members_average(P, boxes, n_mem, name):
+    """An ensemble of networks sharing one descriptor (the 8-network form is what the
+    paper's ANI-2x runs): E and F are the member means, against the oracle's mean over
+    members, in both forms and with every network tiling the tuner may pick."""
+    pos, Z, box = boxes[name]
+    wm = sy.model_weights(WATER, seed=1, n_members=n_mem)
+    ref = orc.evaluate(pos, Z, WATER, wm, box=box)
     for prec, tol in (("fp32", 1e-5), ("bf16", 1e-2)):
-        m = P.NNPModel(WATER, weights=sy.flat_weights(w2), precision=prec, n_members=3)
-        E, F, _ = _run(m, pos, Z, box)
-        assert abs(E[0] - ref["E"]) / len(Z) < (1e-6 if prec == "fp32" else 1e-2)
-        assert rel_rmse(F, ref["F"]) < tol
-        m.close()
+        for v in ((2, 7) if name == "c2" else (-1,)):
+            m = P.NNPModel(WATER, weights=sy.flat_weights(wm), precision=prec, n_members=n_mem)
+            if v >= 0:
+                m.set_variant("network", v)
+            E, F, _ = _run(m, pos, Z, box)
+            assert abs(E[0] - ref["E"]) / len(Z) < (1e-6 if prec == "fp32" else 2e-3)
+            assert rel_rmse(F, ref["F"]) < tol
+            if prec == "bf16":
+                assert worst_atom(F, ref["F"]) < BF16_ATOM_BOUND
+            m.close()
 
 
 def test_seeded_weights_match_generator(P):
