@@ -82,6 +82,13 @@ PROFILE_TAGS = {"c1": "water192", "c2": "water12288", "c3": "water98304", "c5a":
                 "c4": "hcno_batch256", "c5b": "hcno60_mm30000", "c5e": "hcno60_mm30000_charges"}
 CSRC = os.path.join(ROOT, "paper_2604_21441_amd", "csrc")
 CALIB_BYTES = 1 << 30   # --calib-copy: one device copy of this many bytes (read + write)
+# Shader-sequencer counters, two passes of at most eight SQ counters (whole-GPU sums per dispatch).
+SQ_PASSES = (("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_LDS",
+              "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS"),
+             ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_SALU",
+              "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_BUSY_CU_CYCLES"))
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
 
 
 def log(*a):
@@ -174,6 +181,10 @@ def profile_commands(workload):
         f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu --nve 0",
         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/WRITE_SIZE_{workload} -o run -- "
         f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu --nve 0",
+        f"rocprofv3 --pmc {' '.join(SQ_PASSES[0])} --output-format csv -d $OUT/SQA_{workload} -o run -- "
+        f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu --nve 0",
+        f"rocprofv3 --pmc {' '.join(SQ_PASSES[1])} --output-format csv -d $OUT/SQB_{workload} -o run -- "
+        f"{b} --workload {workload} --steps 3 --warmup 1 --no-cpu --nve 0",
         f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/calib_FETCH_SIZE -o run -- {b} --calib-copy",
         f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/calib_WRITE_SIZE -o run -- {b} --calib-copy",
         f"python3 bench.py --summarize-profiles $OUT --workload {workload}",
@@ -256,6 +267,47 @@ def summarize_profiles(out_dir, workload):
     with open(os.path.join(dest, f"nnp_compute_{tag}_kernels.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     log(f"[bench] wrote {dest}/nnp_compute_{tag}_kernels.md and _traffic.json ({len(kernels)} kernels)")
+    # shader-sequencer counters, when their passes were collected
+    sq = {}
+    for pi, names in enumerate(SQ_PASSES):
+        path = os.path.join(out_dir, f"SQ{'AB'[pi]}_{workload}", "run_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        for (k, cn), (v, nd) in _counter_means(path).items():
+            if k.startswith("k_"):
+                sq.setdefault(k, {})[cn] = v
+    if not sq:
+        return
+    lines = [f"# Shader-sequencer counters: {WORKLOADS[workload]['desc']}", "",
+             "Per-dispatch means of whole-GPU counter sums (rocprofv3 --pmc, two passes of eight SQ",
+             "counters; commands in the kernels summary of this workload).  Derived columns:",
+             f"* MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / ({N_SIMD} SIMDs x kernel duration x {CLOCK_HZ / 1e9} GHz),",
+             "  the duration being the kernel-trace average above;",
+             "* VALU/wave and MFMA/wave = SQ_INSTS_VALU / SQ_WAVES and SQ_INSTS_MFMA / SQ_WAVES",
+             "  (VALU counts include the MFMA instructions);",
+             "* LDS conflict share = SQ_LDS_BANK_CONFLICT / (SQ_ACTIVE_INST_LDS + SQ_LDS_BANK_CONFLICT);",
+             "* wait share = SQ_WAIT_ANY / SQ_WAVE_CYCLES (waves waiting on memory counters).", "",
+             "| kernel | waves | VALU/wave | MFMA/wave | MFMA busy | LDS instr/wave | LDS conflict share | "
+             "wait share | VMEM rd/wave | VMEM wr/wave |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, e in sorted(sq.items(), key=lambda kv: -kernels.get(kv[0], {}).get("share_pct", 0.0)):
+        waves = e.get("SQ_WAVES", 0.0) or float("nan")
+        dur = kernels.get(k, {}).get("avg_us")
+        busy = e.get("SQ_VALU_MFMA_BUSY_CYCLES")
+        mf = (busy / (N_SIMD * dur * 1e-6 * CLOCK_HZ)) if (busy is not None and dur) else None
+        lds_a, lds_c = e.get("SQ_ACTIVE_INST_LDS", 0.0), e.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        conf = lds_c / (lds_a + lds_c) if lds_a + lds_c > 0 else None
+        wc = e.get("SQ_WAVE_CYCLES")
+        wait = e.get("SQ_WAIT_ANY", 0.0) / wc if wc else None
+        fmt = lambda x, spec: "" if x is None else format(x, spec)
+        lines.append(f"| `{k}` | {waves:.0f} | {fmt(e.get('SQ_INSTS_VALU', 0.0) / waves, '.0f')} | "
+                     f"{fmt(e.get('SQ_INSTS_MFMA', 0.0) / waves, '.0f')} | {fmt(mf, '.3f')} | "
+                     f"{fmt(e.get('SQ_INSTS_LDS', 0.0) / waves, '.0f')} | {fmt(conf, '.2f')} | {fmt(wait, '.2f')} | "
+                     f"{fmt(e.get('SQ_INSTS_VMEM_RD', 0.0) / waves, '.1f')} | "
+                     f"{fmt(e.get('SQ_INSTS_VMEM_WR', 0.0) / waves, '.1f')} |")
+    with open(os.path.join(dest, f"nnp_compute_{tag}_sq.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log(f"[bench] wrote {dest}/nnp_compute_{tag}_sq.md ({len(sq)} kernels)")
 
 
 def network_flops_per_atom(widths):
