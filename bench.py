@@ -619,8 +619,12 @@ def main(argv=None):
             dF = r["F"][a] - ref["F"][a]
             entry["force_rel_rmse"] = float(np.linalg.norm(dF) / np.linalg.norm(ref["F"][a]))
             entry["force_rmse_eV_per_A"] = float(np.sqrt(np.mean(dF ** 2)))
+            # worst NNP atom against the RMS NNP-atom force (MM atoms, whose forces are far
+            # smaller, would make the ratio meaningless)
+            nn = min(n, a.size)
+            dFn, Fn = dF[:nn], ref["F"][a][:nn]
             entry["worst_atom_err_over_rms_force"] = float(
-                np.linalg.norm(dF, axis=1).max() / np.sqrt(np.mean(np.sum(ref["F"][a] ** 2, axis=1))))
+                np.linalg.norm(dFn, axis=1).max() / np.sqrt(np.mean(np.sum(Fn ** 2, axis=1))))
             if ref["E"] is not None:
                 sizes = np.diff(inp["offsets"]) if inp["offsets"] is not None else np.array([n])
                 entry["energy_err_per_atom_eV"] = float(np.max(np.abs(r["E"] - ref["E"]) / sizes))
