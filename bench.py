@@ -122,7 +122,8 @@ def stage_kernel(stage, variants, prec, cfg, periodic=True):
     if stage == "neighbours":
         return "k_neighbours" if v.get("neighbours", 0) == 0 else "k_neighbours_cell"
     if stage == "descriptor":
-        return ["k_desc_fwd", "k_desc_fwd_rows<16>", "k_desc_fwd_rows<8>"][v.get("descriptor", 1)]
+        return ["k_desc_fwd", "k_desc_fwd_rows<16>", "k_desc_fwd_rows<8>", "k_desc_fwd_pool<2>",
+                "k_desc_fwd_pool<4>"][v.get("descriptor", 1)]
     if stage == "network":
         nv = v.get("network", 2)
         dims = f"{k0}, {widths[1]}, {widths[2]}, {widths[3]}, {bf}"

@@ -309,7 +309,8 @@ nnp_status nnp_read_buffer(nnp_model* m, nnp_buffer which, void* dst_host, size_
  * register-resident wavefronts or row-split workgroups of 16, 32 or 64 atoms,
  * or of 32 atoms with 16 for the smallest species, with four or eight
  * wavefronts;
- * descriptor forward: a wavefront, a 16-lane or an 8-lane row per atom; descriptor
+ * descriptor forward: a wavefront, a 16-lane or an 8-lane row per atom, or
+ * wavefronts of two or four atoms sharing their lanes over chunks; descriptor
  * adjoint: a wavefront or half a wavefront per atom, and a wide-load form of
  * its reverse-slot search; neighbour search: one
  * wavefront per atom, or several per cell sharing its centre atoms).
@@ -342,7 +343,9 @@ typedef enum {
  *   neighbours: 0 one wavefront per atom; 1 / 2 / 3 wavefronts per cell with
  *     about 8 / 5 / 3 centre atoms each (with a single bin, 0 is used);
  *   descriptor forward: 0 one wavefront per atom; 1 / 2 one 16-lane / 8-lane
- *     row per atom;
+ *     row per atom; 3 / 4 two / four atoms per wavefront, their radial
+ *     segments and angular classes cut into equal chunks, one per lane
+ *     (for several elements, whose classes hold few pairs each);
  *   network: 0 register-resident wavefronts; 1 / 2 / 3 row-split workgroups
  *     of 16 / 32 / 64 atoms (64 for water-sized networks only, wider ones
  *     use 32); 4 workgroups of 32 atoms, 16 for the species with the fewest

@@ -432,6 +432,337 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pool kernel: AW atoms per wavefront, the lanes balanced over the work of
+// all of them.
+//
+// The radial neighbours of one (atom, neighbour species) and the angular
+// pairs of one (atom, species-pair class) form a unit.  The wavefront cuts
+// its units into chunks of at most C items, C being (within a few steps) the
+// smallest size for which the chunks fit its 64 lanes, and each lane sums one
+// chunk's block in registers.  The chunks of a unit then add up pairwise in
+// a tree (chunk c + d into chunk c for c a multiple of 2d, d = 1, 2, 4, ...,
+// 16 values at a time through LDS), and the unit's first chunk stores the
+// block in the descriptor row.  With
+// several elements a class holds few pairs (about 14 per class for H/C/N/O
+// molecules against 17 angular neighbours): the row kernels then leave most
+// lanes of a row idle and pay a 32-value cross-lane reduction per class,
+// which this kernel avoids.  Adding the partials with LDS float atomics
+// instead was several times slower.  The radial phase runs first, so that
+// the partial rows can share LDS with the angular geometry (each is dead
+// while the other is live).
+constexpr int kPoolPitch = 20;   // LDS row of one lane's 16 partial sums (16-byte aligned)
+
+// Inclusive prefix sum / maximum over the 64 lanes with DPP: row shifts
+// within each 16-lane row, then the row broadcasts of lanes 15 and 31.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <bool MAX>
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+  // out-of-row sources read as the identity (0 for the sums; counts and
+  // packed owners here are never negative, so 0 also serves the maximum)
+#define NNP_SCAN_STEP(CTRL, RM)                                               \
+  {                                                                           \
+    const int t = __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xF, true);     \
+    v = MAX ? max(v, t) : v + t;                                              \
+  }
+  NNP_SCAN_STEP(kDppRowShr1, 0xF)
+  NNP_SCAN_STEP(kDppRowShr2, 0xF)
+  NNP_SCAN_STEP(kDppRowShr4, 0xF)
+  NNP_SCAN_STEP(kDppRowShr8, 0xF)
+  NNP_SCAN_STEP(kDppRowBcast15, 0xA)
+  NNP_SCAN_STEP(kDppRowBcast31, 0xC)
+#undef NNP_SCAN_STEP
+  return v;
+}
+
+__device__ __forceinline__ int wave_total(int v) {
+  return __builtin_amdgcn_readlane(wave_scan_dpp<false>(v), 63);
+}
+
+// ceil(x / C) for 0 <= x < 2^20 and C >= 1, with rC = 1 / C: the FP32
+// quotient is within one of the true one, and one correction each way fixes it.
+__device__ __forceinline__ int ceil_div(int x, int C, float rC) {
+  if (x <= 0) return 0;
+  const int y = x - 1;
+  int q = (int)((float)y * rC);
+  q -= q * C > y ? 1 : 0;
+  q += (q + 1) * C <= y ? 1 : 0;
+  return q + 1;
+}
+
+// Chunk size for unit sizes cnt (one unit per lane, 0 elsewhere): with U
+// non-empty units and N items, C = ceil(N / (64 - U)) always fits, since the
+// chunk count is below N / C + U; smaller sizes are tried while they still fit.
+__device__ __forceinline__ int pool_chunk(int cnt) {
+  const int N = wave_total(cnt);
+  if (N == 0) return 0;
+  const int U = (int)__popcll(__ballot(cnt > 0));
+  int C = (N + 63 - U) / (64 - U);   // uniform: scalar arithmetic
+  for (int step = 0; step < 3 && C > 1; ++step) {
+    const int k = ceil_div(cnt, C - 1, __builtin_amdgcn_rcpf((float)(C - 1)));
+    if (wave_total(k) > 64) break;
+    --C;
+  }
+  return C;
+}
+
+// The wavefronts of a pool workgroup work independently, each in its own LDS
+// slice, and synchronise only among their own lanes: LDS accesses of one
+// wavefront complete in order, so keeping the compiler from moving them
+// across this point is enough.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hands the chunks out to the lanes in unit order: lane l < K gets unit *unit
+// (the lane that holds it), chunk *chunk of that unit and the unit's chunk
+// count *nunit; other lanes get unit -1.  Returns the largest chunk count.
+__device__ __forceinline__ int pool_assign(int cnt, int C, int lane, int* owner, int* unit, int* chunk,
+                                           int* nunit) {
+  const int nch = C > 0 ? ceil_div(cnt, C, __builtin_amdgcn_rcpf((float)C)) : 0;
+  const int incl = wave_scan_dpp<false>(nch);
+  const int K = __builtin_amdgcn_readlane(incl, 63);
+  const int excl = incl - nch;
+  owner[lane] = 0;
+  wave_sync();
+  if (nch > 0) owner[excl] = ((lane + 1) << 8) | excl;
+  wave_sync();
+  const int o = wave_scan_dpp<true>(owner[lane]);
+  *unit = lane < K ? (o >> 8) - 1 : -1;
+  *chunk = lane < K ? lane - (o & 255) : 0;
+  *nunit = __shfl(nch, max(*unit, 0), 64);
+  return __builtin_amdgcn_readlane(wave_scan_dpp<true>(nch), 63);
+}
+
+// Pairwise tree over the chunks of each unit (chunks of a unit sit on
+// consecutive lanes): chunk c + d adds into chunk c for c a multiple of 2d,
+// through this lane's LDS row, until chunk 0 holds the unit's sums.
+__device__ __forceinline__ void pool_tree16(float* v, float* part, int lane, int unit, int chunk, int nunit,
+                                            int maxn) {
+  for (int d = 1; d < maxn; d *= 2) {
+    wave_sync();
+    if (unit >= 0 && (chunk & (2 * d - 1)) == d) {
+      float4* row = reinterpret_cast<float4*>(part + lane * kPoolPitch);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) row[e] = make_float4(v[4 * e], v[4 * e + 1], v[4 * e + 2], v[4 * e + 3]);
+    }
+    wave_sync();
+    if (unit >= 0 && (chunk & (2 * d - 1)) == 0 && chunk + d < nunit) {
+      const float4* row = reinterpret_cast<const float4*>(part + (lane + d) * kPoolPitch);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float4 w = row[e];
+        v[4 * e] += w.x;
+        v[4 * e + 1] += w.y;
+        v[4 * e + 2] += w.z;
+        v[4 * e + 3] += w.w;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void store16(float* dst, const float* v) {
+  float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) d4[e] = make_float4(v[4 * e], v[4 * e + 1], v[4 * e + 2], v[4 * e + 3]);
+}
+
+template <int AW>
+__global__ __launch_bounds__(256) void k_desc_fwd_pool(FwdArgs a, DescParams p, Geometry geo) {
+  static_assert(AW >= 1 && AW * kMaxPairs <= 40, "units must leave lanes for the chunks");
+  extern __shared__ float4 smem_pool[];
+  const int S = p.S, P = p.P, S1 = S + 1;
+  // per wavefront: [angular geometry | partial rows (aliased: never live together)] [owner]
+  const int area = (max(AW * a.max_ang * 5, 64 * kPoolPitch) + 3) & ~3;   // floats
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  float4* smem_p = smem_pool + wave * ((area + 64) / 4);
+  float4* G = smem_p;                                             // [AW][max_ang] (u, r hq)
+  float* W = reinterpret_cast<float*>(G + AW * a.max_ang);        // [AW][max_ang] fc sq_pref
+  float* part = reinterpret_cast<float*>(smem_p);                 // [64][kPoolPitch]
+  int* owner = reinterpret_cast<int*>(smem_p) + area;             // [64]
+  const int li0 = (xcd_block(blockIdx.x, gridDim.x) * 4 + wave) * AW;
+  const Consts c = make_consts(p);
+  int slot[AW], na[AW];
+  int nat = 0;
+#pragma unroll
+  for (int t = 0; t < AW; ++t) {
+    slot[t] = li0 + t < a.n ? a.order[li0 + t] : 0;
+    na[t] = li0 + t < a.n ? a.ang_off[(int64_t)slot[t] * S1 + S] : 0;
+    nat += na[t];
+  }
+  auto atom_of = [&](int t) {
+    int ii = slot[0];
+#pragma unroll
+    for (int k = 1; k < AW; ++k) ii = t == k ? slot[k] : ii;
+    return ii;
+  };
+
+  // ---- angular units (lane t * kMaxPairs + q), set up first so that their
+  // loads and the first pass of the geometry loads overlap the radial phase
+  uint64_t pairs = 0;   // species pairs of the classes, four bits each (uniform)
+#pragma unroll
+  for (int k = 0; k < kMaxPairs; ++k) pairs |= (uint64_t)(p.pair_a[k] | (p.pair_b[k] << 2)) << (4 * k);
+  int T = 0, oa = 0, kb = 0, nB = 0, same = 0;
+  {
+    const int t = lane / kMaxPairs, q = lane % kMaxPairs;
+    if (t < AW && q < P && li0 + t < a.n) {
+      const int code = (int)(pairs >> (4 * q)) & 15;
+      const int sa = code & 3, sb = code >> 2;
+      const int ii = atom_of(t);
+      const int* aoff = a.ang_off + (int64_t)ii * S1;
+      oa = aoff[sa];
+      const int nA = aoff[sa + 1] - oa;
+      const int ob = aoff[sb];
+      nB = aoff[sb + 1] - ob;
+      same = sa == sb;
+      kb = same ? oa : ob;
+      T = same ? nA * (nA - 1) / 2 : nA * nB;
+      if (T == 0) {   // no pairs in this class
+        const float zero[kRadShifts] = {};
+        float* dst = a.x + (int64_t)ii * p.stride + S * kRadShifts + q * kAngShifts * kAngSects;
+        store16(dst, zero);
+        store16(dst + 16, zero);
+      }
+    }
+  }
+  // angular neighbour geometry, flattened over the atoms: the first pass is
+  // loaded now and stored to LDS after the radial phase (whose partial rows
+  // share that LDS)
+  auto split = [&](int f, int* tt, int* uu) {
+    int t = 0, u = f;
+#pragma unroll
+    for (int k = 0; k + 1 < AW; ++k)
+      if (t == k && u >= na[k]) { u -= na[k]; t = k + 1; }
+    *tt = t;
+    *uu = u;
+  };
+  int g_t = 0, g_u = 0, g_ii = 0;
+  float4 g_pi = make_float4(0.f, 0.f, 0.f, 0.f), g_pj = g_pi;
+  if (lane < nat) {
+    split(lane, &g_t, &g_u);
+    g_ii = atom_of(g_t);
+    g_pi = a.spos[g_ii];
+    g_pj = a.spos[a.ang[(int64_t)g_ii * a.max_ang + g_u]];
+  }
+
+  // ---- radial units (lane t * kMaxSpecies + s) and chunks
+  {
+    const int t = lane / kMaxSpecies, s = lane % kMaxSpecies;
+    int beg = 0, cnt = 0, ii = 0;
+    if (t < AW && s < S && li0 + t < a.n) {
+      ii = atom_of(t);
+      const int* roff = a.rad_off + (int64_t)ii * S1;
+      beg = roff[s];
+      cnt = roff[s + 1] - beg;
+      if (cnt == 0) {   // no neighbours of this species
+        const float zero[kRadShifts] = {};
+        store16(a.x + (int64_t)ii * p.stride + s * kRadShifts, zero);
+      }
+    }
+    const int C = pool_chunk(cnt);
+    int unit, chunk, nunit;
+    const int maxn = pool_assign(cnt, C, lane, owner, &unit, &chunk, &nunit);
+    const int src = max(unit, 0);
+    const int ub = __shfl(beg, src, 64), ue = __shfl(beg + cnt, src, 64), ui = __shfl(ii, src, 64);
+    float acc[kRadShifts];
+#pragma unroll
+    for (int k = 0; k < kRadShifts; ++k) acc[k] = 0.f;
+    if (unit >= 0) {
+      const int b0 = ub + chunk * C, b1 = min(b0 + C, ue);
+      const float4 pi = a.spos[ui];
+      const MinImage mi = min_image_at(geo, ui);
+      const int* rrow = a.rad + (int64_t)ui * a.max_rad;
+      for (int q = b0; q < b1; ++q) {
+#pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
+        const Geo d = displacement(pi, a.spos[rrow[q]], mi);
+        const float fc = fmaf(0.5f, cos_rev(d.r * c.inv2rc), 0.5f);
+        const float rs = d.r * p.sq_eta_r;
+#pragma unroll
+        for (int k = 0; k < kRadShifts; ++k) {
+          const float tt = rs - p.rad_shift_s[k];
+          acc[k] = fmaf(ex2(-(tt * tt)), fc, acc[k]);
+        }
+      }
+    }
+    pool_tree16(acc, part, lane, unit, chunk, nunit, maxn);
+    if (unit >= 0 && chunk == 0) store16(a.x + (int64_t)ui * p.stride + (src % kMaxSpecies) * kRadShifts, acc);
+  }
+  wave_sync();
+
+  // ---- angular geometry to LDS
+  for (int f = lane; f < nat; f += 64) {
+    if (f >= 64) {
+      split(f, &g_t, &g_u);
+      g_ii = atom_of(g_t);
+      g_pi = a.spos[g_ii];
+      g_pj = a.spos[a.ang[(int64_t)g_ii * a.max_ang + g_u]];
+    }
+    const Geo d = displacement(g_pi, g_pj, min_image_at(geo, g_ii));
+    G[g_t * a.max_ang + g_u] = make_float4(d.dx * d.ir, d.dy * d.ir, d.dz * d.ir, d.r * p.hq_eta_a);
+    W[g_t * a.max_ang + g_u] = (0.5f * cos_rev(d.r * c.inv2rca) + 0.5f) * p.sq_pref;
+  }
+  wave_sync();
+
+  // ---- angular chunks
+  const int C = pool_chunk(T);
+  int unit, chunk, nunit;
+  const int maxn = pool_assign(T, C, lane, owner, &unit, &chunk, &nunit);
+  const int src = max(unit, 0);
+  const int uT = __shfl(T, src, 64), uoa = __shfl(oa, src, 64), ukb = __shfl(kb, src, 64);
+  const int unB = __shfl(nB, src, 64), usame = __shfl(same, src, 64);
+  const int ut = src / kMaxPairs;
+  float acc[kAngShifts * kAngSects];
+#pragma unroll
+  for (int e = 0; e < kAngShifts * kAngSects; ++e) acc[e] = 0.f;
+  if (unit >= 0) {
+    const float4* Gt = G + ut * a.max_ang;
+    const float* Wt = W + ut * a.max_ang;
+    const int r0 = chunk * C, r1 = min(r0 + C, uT);
+    // (inner, outer) walk: same species k-major over j < k (inner j, limit k),
+    // two species j-major (inner k, limit nB)
+    int j, k;
+    pair_start(r0, usame != 0, unB, &j, &k);
+    int in = usame ? j : k, out = usame ? k : j;
+    for (int r = r0; r < r1; ++r) {
+      const int jj = usame ? in : out, kk = usame ? out : in;
+      const float4 gj = Gt[uoa + jj], gk = Gt[ukb + kk];
+      const float F = Wt[uoa + jj] * Wt[ukb + kk];
+      const float cs = gj.x * gk.x + gj.y * gk.y + gj.z * gk.z;
+      const float ct = 0.95f * cs;
+      const float sn = __builtin_amdgcn_sqrtf(1.f - ct * ct);
+      const float rb = gj.w + gk.w;
+      float A[kAngSects];
+#pragma unroll
+      for (int n = 0; n < kAngSects; ++n) {
+        const float base = 1.f + ct * p.cos_sect[n] + sn * p.sin_sect[n];
+        A[n] = F * ex2(p.zeta * lg2(base));
+      }
+#pragma unroll
+      for (int m = 0; m < kAngShifts; ++m) {
+        const float tt = rb - p.ang_shift_s[m];
+        const float B = ex2(-(tt * tt));
+#pragma unroll
+        for (int n = 0; n < kAngSects; ++n) acc[m * kAngSects + n] = fmaf(B, A[n], acc[m * kAngSects + n]);
+      }
+      ++in;
+      const bool wrap = in == (usame ? out : unB);
+      in = wrap ? 0 : in;
+      out += wrap ? 1 : 0;
+    }
+  }
+  // the unit sums in two halves of 16 (the geometry is dead from here on)
+  constexpr int B = kAngShifts * kAngSects, H = B / 2;
+  float* dst = a.x + (int64_t)atom_of(ut) * p.stride + S * kRadShifts + (src % kMaxPairs) * B;
+  pool_tree16(acc, part, lane, unit, chunk, nunit, maxn);
+  if (unit >= 0 && chunk == 0) store16(dst, acc);
+  pool_tree16(acc + H, part, lane, unit, chunk, nunit, maxn);
+  if (unit >= 0 && chunk == 0) store16(dst + H, acc + H);
+}
+
 // Adjoint, one wavefront per centre atom i (no global atomics).
 //
 // E depends on d_ij = x_j - x_i, so a pair vector v = dE/d(d_ij) contributes
@@ -855,7 +1186,8 @@ hipError_t launch_link_redistribute(nnp_model& m, const float* pos, double* forc
 
 // Forward descriptor variants: 0 = one wavefront per atom, 1 = one 16-lane
 // row per atom (default), 2 = one 8-lane row per atom (fewer idle lanes,
-// half the wavefronts: for large systems).
+// half the wavefronts: for large systems), 3 and 4 = the pool kernel with two
+// and four atoms per wavefront (many elements: few pairs per class).
 int descriptor_variant(const nnp_model& m, int n) {
   const int v = stage_variant(m, kTuneDescriptor, n);
   return v >= 0 ? v : 1;
@@ -875,7 +1207,16 @@ hipError_t launch_descriptor_fwd(nnp_model& m, int n, hipStream_t st) {
   a.n = n;
   a.x = m.d_x;
   const int v = descriptor_variant(m, n);
-  if (v == 1) {
+  if (v == 3 || v == 4) {
+    const int aw = v == 3 ? 2 : 4;
+    const size_t area = (std::max((size_t)aw * m.max_ang * 5, (size_t)64 * kPoolPitch) + 3) & ~(size_t)3;
+    const size_t lds = 4 * sizeof(float) * (area + 64);   // four wavefronts, each with its own slice
+    const unsigned blocks = (unsigned)((n + 4 * aw - 1) / (4 * aw));
+    if (v == 3)
+      hipLaunchKernelGGL(k_desc_fwd_pool<2>, dim3(blocks), dim3(256), lds, st, a, m.dp, m.geo);
+    else
+      hipLaunchKernelGGL(k_desc_fwd_pool<4>, dim3(blocks), dim3(256), lds, st, a, m.dp, m.geo);
+  } else if (v == 1) {
     const size_t lds = (sizeof(float4) + sizeof(float)) * 16 * (size_t)m.max_ang;
     hipLaunchKernelGGL(k_desc_fwd_rows<16>, dim3((n + 15) / 16), dim3(256), lds, st, a, m.dp, m.geo);
   } else if (v == 2) {

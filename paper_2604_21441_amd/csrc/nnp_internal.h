@@ -330,7 +330,7 @@ int adjoint_variant(const nnp_model& m, int n);
 // Variant of a tuned stage: the candidate being timed, else the pinned one,
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
-constexpr int kStageVariants[kTuneStages] = {4, 3, 10, 3};
+constexpr int kStageVariants[kTuneStages] = {4, 5, 10, 3};
 int size_bucket(int n);
 
 // workspace (api.cpp): capacities for a call of up to max_atoms atoms, and the

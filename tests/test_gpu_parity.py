@@ -305,8 +305,8 @@ def test_autotune_keeps_results(P, w_water):
         torch.cuda.synchronize()
         E0, F0 = E0.clone(), F0.clone()
         chosen = m.autotune(3)
-        assert 0 <= chosen["network"] < 8 and chosen["neighbours"] in (0, 1, 2, 3)
-        assert chosen["descriptor"] in (0, 1, 2) and chosen["adjoint"] in (0, 1, 2)
+        assert 0 <= chosen["network"] < 10 and chosen["neighbours"] in (0, 1, 2, 3)
+        assert chosen["descriptor"] in (0, 1, 2, 3, 4) and chosen["adjoint"] in (0, 1, 2)
         E1, F1, _ = m.compute(d, Z, box)
         torch.cuda.synchronize()
         assert m.status() == 0
@@ -322,7 +322,7 @@ def test_autotune_keeps_results(P, w_water):
 
 VARIANTS = [("neighbours", 0, "fp32"), ("neighbours", 1, "fp32"), ("neighbours", 2, "fp32"),
             ("neighbours", 3, "fp32"), ("descriptor", 0, "fp32"), ("descriptor", 2, "fp32"),
-            ("descriptor", 1, "fp32"), ("network", 0, "fp32"), ("network", 1, "fp32"), ("network", 2, "fp32"),
+            ("descriptor", 1, "fp32"), ("descriptor", 3, "fp32"), ("descriptor", 4, "fp32"), ("network", 0, "fp32"), ("network", 1, "fp32"), ("network", 2, "fp32"),
             ("network", 3, "fp32"), ("network", 4, "fp32"), ("network", 5, "fp32"), ("network", 6, "fp32"),
             ("network", 7, "fp32"), ("network", 0, "bf16"), ("network", 1, "bf16"), ("network", 2, "bf16"),
             ("network", 3, "bf16"), ("network", 4, "bf16"), ("network", 5, "bf16"), ("network", 6, "bf16"),
@@ -352,7 +352,7 @@ def test_pinned_variant_parity(P, w_water, boxes, oracle_res, stage, variant, pr
     xr[perm] = x
     err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
     assert err.max() < 1e-5, err.max()
-    nvar = {"network": 10, "neighbours": 4, "descriptor": 3, "adjoint": 3}[stage]
+    nvar = {"network": 10, "neighbours": 4, "descriptor": 5, "adjoint": 3}[stage]
     for bad in ((stage, nvar), (4, 0), (stage, -2)):
         with pytest.raises(P.NNPError) as ex:
             m.set_variant(*bad)
@@ -640,6 +640,36 @@ def test_link_atoms(P, w_hcno):
     ref = orc.evaluate(pos, Z, HCNO, w_hcno, nnp_idx=idx)
     assert abs(E[0] - ref["E"]) / idx.size < 1e-6
     assert rel_rmse(F, ref["F"]) < 1e-5
+    m.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_descriptor_variants_hcno_batch(P, w_hcno, variant):
+    """Each descriptor kernel on an uneven batch of H/C/N/O molecules (ten species-pair
+    classes with few pairs each): descriptor rows, molecule energies and forces against the
+    oracle, and two calls bitwise equal (the pool kernels add chunk sums with LDS atomics)."""
+    pos, Z, off = sy.walk_batch(24, seed=7)
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
+    m.set_variant("descriptor", variant)
+    d = torch.from_numpy(pos).cuda()
+    xs = []
+    for _ in range(2):
+        E, F = m.compute_batch(d, Z, off)
+        torch.cuda.synchronize()
+        assert m.status() == 0
+        xs.append(m.read(P._lib.NNP_BUF_DESCRIPTOR)[:, :384].copy())
+    assert np.array_equal(xs[0], xs[1])
+    E, F = E.cpu().numpy(), F.cpu().numpy()
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    xr = np.empty(xs[0].shape)
+    xr[perm] = xs[0]
+    for s in range(len(off) - 1):
+        a, b = off[s], off[s + 1]
+        ref = orc.evaluate(pos[a:b], Z[a:b], HCNO, w_hcno, return_x=True)
+        err = np.linalg.norm(xr[a:b] - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
+        assert err.max() < 5e-6, (s, err.max())
+        assert abs(E[s] - ref["E"]) / (b - a) < 1e-6
+        assert rel_rmse(F[a:b], ref["F"]) < 1e-5
     m.close()
 
 
