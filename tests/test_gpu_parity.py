@@ -673,6 +673,41 @@ def test_descriptor_variants_hcno_batch(P, w_hcno, variant):
     m.close()
 
 
+@pytest.mark.parametrize("variant", [3, 4])
+def test_pool_descriptor_dense_and_isolated(P, w_hcno, variant):
+    """The pool kernels on a dense H/C/N/O cluster (about 35 angular neighbours per atom, so
+    the wavefront's neighbour geometry takes a second pass) plus an isolated atom (every
+    unit empty: its row must be zero): descriptor rows, energy and forces against the oracle."""
+    rng = np.random.default_rng(11)
+    n = 300
+    pos = rng.uniform(0.0, 6.0, size=(n, 3))
+    keep = [0]
+    for k in range(1, n):   # at least 1 A apart: 92 atoms, up to 57 angular neighbours
+        if np.min(np.linalg.norm(pos[keep] - pos[k], axis=1)) > 1.0:
+            keep.append(k)
+    pos = np.concatenate([pos[keep], [[30.0, 30.0, 30.0]]]).astype(np.float32)
+    Z = rng.choice(np.array([1, 6, 7, 8], dtype=np.int32), size=len(pos))
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
+    m.set_variant("descriptor", variant)
+    E, F, _ = _run(m, pos, Z, None)
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    x = m.read(P._lib.NNP_BUF_DESCRIPTOR)[:, :384]
+    xr = np.empty(x.shape)
+    xr[perm] = x
+    ref = orc.evaluate(pos, Z, HCNO, w_hcno, return_x=True)
+    assert np.all(xr[-1] == 0.0)
+    err = np.linalg.norm(xr[:-1] - ref["x"][:-1], axis=1) / np.linalg.norm(ref["x"][:-1], axis=1)
+    assert err.max() < 5e-6, err.max()
+    assert abs(E[0] - ref["E"]) / len(Z) < 1e-6
+    assert rel_rmse(F, ref["F"]) < 1e-5
+    # dense enough that two atoms of a wavefront hold more than 64 angular neighbours
+    # (the second staging pass)
+    d = np.linalg.norm(pos[:-1, None] - pos[None, :-1], axis=2)
+    n_ang = (d < HCNO["rc_ang"]).sum(axis=1) - 1
+    assert n_ang.mean() > 30 and n_ang.max() < 64
+    m.close()
+
+
 # ------------------------------------------------------------------ batching
 def test_batched_open_systems(P, w_hcno):
     pos, Z, off = sy.walk_batch(12, seed=4)
