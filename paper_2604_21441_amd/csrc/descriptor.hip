@@ -20,6 +20,8 @@
 // Transcendentals use the hardware exp2 / log2 / sin / cos / sqrt / rsq
 // instructions (arguments pre-scaled: exp(x) = exp2(x log2 e), cos(pi r/R) =
 // cos of r/(2R) revolutions).
+#include <climits>
+
 #include "nnp_internal.h"
 
 namespace nnp {
@@ -1005,26 +1007,51 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
     const int lo = a.rad_off[(int64_t)j * S1 + si], hi = a.rad_off[(int64_t)j * S1 + si + 1];
     int pos = -1;
     if (wide) {
-      int below = 0;
-      bool hit = false;
+      // lower bound of i in j's segment [lo, hi), 32 entries per round.  The
+      // key of entry e is -inf before lo, +inf from hi on and the (sorted)
+      // entry in between; keys are monotone, so the groups of four whose
+      // first key is below i form a prefix, and the boundary lies in the
+      // last of them (or at the next group's first entry).
       for (int e0 = lo & ~3; e0 < hi; e0 += 32) {
         int4 q[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)   // a load starting before hi stays inside the row (max_rad % 4 == 0)
-          q[u] = e0 + 4 * u < hi ? reinterpret_cast<const int4*>(jrow + e0)[u] : make_int4(0, 0, 0, 0);
+          q[u] = e0 + 4 * u < hi ? reinterpret_cast<const int4*>(jrow + e0)[u]
+                                 : make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX);
+        int g = (e0 < lo || q[0].x < i) ? 1 : 0;   // e0 >= lo - 3: only group 0 can start before lo
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int v[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+        for (int u = 1; u < 8; ++u) g += q[u].x < i ? 1 : 0;
+        int x = 0, at = q[0].x;   // x: keys below i in this round; at: the entry at x
+        if (g > 0) {
+          const int gs = g - 1;
+          int4 sel[8];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int e = e0 + 4 * u + c;
-            const bool in = e >= lo && e < hi;
-            below += (in && v[c] < i) ? 1 : 0;
-            hit = hit || (in && v[c] == i);
+          for (int u = 0; u < 8; ++u) sel[u] = q[u];
+#pragma unroll
+          for (int b = 1; b < 8; b <<= 1)   // multiplexer tree: sel[0] = q[gs]
+#pragma unroll
+            for (int u = 0; u + b < 8; u += 2 * b)
+              if (gs & b) sel[u] = sel[u + b];
+          int nxt = INT_MAX;   // first entry of group gs + 1
+#pragma unroll
+          for (int u = 1; u < 8; ++u) nxt = gs + 1 == u ? q[u].x : nxt;
+          const int eb = e0 + 4 * gs;
+          const int w[4] = {sel[0].x, sel[0].y, sel[0].z, sel[0].w};
+          x = 4 * gs + 1;
+          at = nxt;
+#pragma unroll
+          for (int c = 3; c >= 1; --c) {   // keys are monotone: count those below i
+            const int e = eb + c;
+            const bool less = e < lo || (e < hi && w[c] < i);
+            x += less ? 1 : 0;
           }
+          at = x == 4 * gs + 1 ? w[1] : x == 4 * gs + 2 ? w[2] : x == 4 * gs + 3 ? w[3] : nxt;
+        }
+        if (x < 32) {   // the first key >= i is in this round
+          if (e0 + x < hi && at == i) pos = e0 + x;
+          break;
         }
       }
-      if (hit) pos = lo + below;
     } else {
       int l = lo, h = hi - 1;
       while (l < h) {
