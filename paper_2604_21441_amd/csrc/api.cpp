@@ -388,6 +388,15 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
     for (int k = 0; k < kRadShifts; ++k) p.rad_shift_s[k] = (float)(sr * (double)cfg->rad_shift_host[k]);
     for (int k = 0; k < kAngShifts; ++k) p.ang_shift_s[k] = (float)(sa * (double)cfg->ang_shift_host[k]);
   }
+  {
+    const float pi = 3.14159265358979323846f;
+    p.inv2rc = 0.5f / p.rc_rad;
+    p.inv2rca = 0.5f / p.rc_ang;
+    p.dfc_r = -0.5f * pi / p.rc_rad;
+    p.dfc_a = -0.5f * pi / p.rc_ang;
+    p.c1_rad = -2.f * p.eta_rad / p.sq_eta_r;
+    p.c_sdr = -p.eta_ang / p.hq_eta_a;
+  }
   p.mm_cutoff = cfg->mm_cutoff;
   p.ke = (float)cfg->ke_coulomb;
   p.S = S;
@@ -404,6 +413,9 @@ nnp_status nnp_create(const nnp_config* cfg, uint64_t seed, const float* weights
       p.class_of[b][a] = q;
       ++q;
     }
+  p.class_tab = 0;
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < S; ++b) p.class_tab |= (uint64_t)p.class_of[a][b] << (4 * (4 * a + b));
 
   // weights
   size_t per_species = 0;

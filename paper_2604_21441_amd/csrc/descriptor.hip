@@ -67,10 +67,10 @@ __device__ __forceinline__ Consts make_consts(const DescParams& p) {
   Consts c;
   c.eta_r_l2 = p.eta_rad * kLog2e;
   c.eta_a_l2 = p.eta_ang * kLog2e;
-  c.inv2rc = 0.5f / p.rc_rad;
-  c.inv2rca = 0.5f / p.rc_ang;
-  c.dfc_r = -0.5f * 3.14159265358979323846f / p.rc_rad;
-  c.dfc_a = -0.5f * 3.14159265358979323846f / p.rc_ang;
+  c.inv2rc = p.inv2rc;
+  c.inv2rca = p.inv2rca;
+  c.dfc_r = p.dfc_r;
+  c.dfc_a = p.dfc_a;
   return c;
 }
 
@@ -862,7 +862,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
   __syncthreads();
   // 2. radial pairs
   {
-    const float c1 = -2.f * p.eta_rad / p.sq_eta_r;   // d/dr of -(r sq - Rs sq)^2 per (r sq - Rs sq), in ln units
+    const float c1 = p.c1_rad;   // d/dr of -(r sq - Rs sq)^2 per (r sq - Rs sq), in ln units
     for (int t = lane; t < nr; t += LANES) {
 #pragma clang fp contract(off)   // keep r sq in a register: one SGPR operand per shift
       const float4 pj = a.spos[rrow[t]];
@@ -906,7 +906,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
     if (k * (k - 1) / 2 > r0) --k;
     if ((k + 1) * k / 2 <= r0) ++k;
     int j = r0 - k * (k - 1) / 2;
-    const float c_sdr = -p.eta_ang / p.hq_eta_a;     // d rbar-term per (rbar sa - Ra sa), sa = 2 hq
+    const float c_sdr = p.c_sdr;     // d rbar-term per (rbar sa - Ra sa), sa = 2 hq
     const float c_dc = p.zeta * 0.95f;
     float kx = 0.f, ky = 0.f, kz = 0.f;   // running total of the current k
     float4 k1 = G1[k], k2 = G2[k];
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(64) void k_desc_bwd(BwdArgs a, DescParams p, Geomet
       const float4 j1 = G1[j], j2 = G2[j];
       const int wj = __float_as_int(j2.w), wk = __float_as_int(k2.w);
       const int sj = wj & 7, sk = wk & 7;                   // sj <= sk (rows are grouped by species)
-      const int q = sj * p.S - (sj * (sj - 1)) / 2 + (sk - sj);
+      const int q = (int)(p.class_tab >> (4 * (4 * sj + sk))) & 15;
       const float4* g4 = reinterpret_cast<const float4*>(gl + p.S * kRadShifts + q * kAngShifts * kAngSects);
       const float cs = fmaf(j1.x, k1.x, fmaf(j1.y, k1.y, j1.z * k1.z));
       const float ct = 0.95f * cs;

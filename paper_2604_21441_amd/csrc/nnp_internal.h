@@ -97,6 +97,13 @@ struct DescParams {
   // distance enters as r_j hq + r_k hq with hq = sq / 2; sq_pref^2 = 2^(1-zeta).
   float sq_eta_r, hq_eta_a, sq_pref;
   float rad_shift_s[kRadShifts], ang_shift_s[kAngShifts];
+  // Derived FP32 constants, computed once on the host with the same IEEE
+  // operations the kernels would use: 1/(2 Rc) and 1/(2 Rca) (cos(pi r / Rc) =
+  // cos of r/(2 Rc) revolutions), -pi/(2 Rc) and -pi/(2 Rca) (the cutoff
+  // derivative factor), -2 eta_r / sq_eta_r and -eta_a / hq_eta_a (the chain
+  // factors of the scaled Gaussians in the adjoint).
+  float inv2rc, inv2rca, dfc_r, dfc_a, c1_rad, c_sdr;
+  uint64_t class_tab;                   // class of species pair (a, b) in bits 4 (4 a + b) .. +3
   float mm_cutoff, ke;
   int S, P, D, stride;                  // species, pair classes, descriptor length, row stride
   int extra;                            // 1 if the MM potential is the last input
