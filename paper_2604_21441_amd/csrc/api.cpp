@@ -84,6 +84,7 @@ size_t carve_workspace(const nnp_model& m, Workspace& w, char* base) {
   take(w.d_bin_count, (size_t)w.max_bins);
   take(w.d_bin_start, (size_t)w.max_bins + 1);
   take(w.d_cmstart, (size_t)w.max_bins);
+  take(w.d_scan_part, 2 * ((size_t)w.max_bins / kScanPartChunk + 2));
   take(w.d_order, n);
   take(w.d_nbr_rad, n * w.max_rad);
   take(w.d_nbr_ang, n * w.max_ang);

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(const float* __restrict__ pos,
 // straight from memory are several times slower); each thread scans
 // PER consecutive entries of the staged chunk, PER being the smallest power
 // of two for which one chunk holds the whole histogram (at most 16; larger
-// histograms take several chunks).  Sizing the chunk to the histogram
+// histograms go to the many-workgroup scan, k_scan_part and k_scan_fin).  Sizing the chunk to the histogram
 // matters: one workgroup does all of this work, and with 16 entries per
 // thread a 1,024-bin scan took 6.8 us.  The histogram itself is left as it
 // is (the bin sort clears it).
@@ -221,54 +221,89 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const int* __restrict__ c
       if (i < nb) start[i] = bufc[scan_pad<PER>(i)];
     }
     if (threadIdx.x == 0) start[nb] = carry;
-    return;
   }
-  // bin-major: bin b carries T[b], the sum of its species counts
-  for (int c0 = 0; c0 < n_bins; c0 += kScanThreads * PER) {
+}
+
+// Histograms beyond one chunk: the same two scans over many workgroups, in
+// two launches.  Workgroup w < ca takes species-major chunk w (counts), the
+// others bin-major chunk w - ca (per-bin totals over the species); each chunk
+// holds kScanPartChunk = kScanThreads * 4 entries.  k_scan_part writes the
+// chunk totals, k_scan_fin scans each chunk again starting from the sum of
+// the earlier chunks of its order.  One workgroup scanning 35,152 bins took
+// 38 us.
+constexpr int kScanPartPer = kScanPartChunk / kScanThreads;
+static_assert(kScanPartPer * kScanThreads == kScanPartChunk, "whole entries per thread");
+
+__device__ __forceinline__ int scan_entry(const int* __restrict__ count, bool bin_major, int e, int S, int n_bins) {
+  if (!bin_major) return count[e];
+  int t = 0;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
-      int t = 0;
+  for (int s = 0; s < kMaxSpecies; ++s)
+    if (s < S) t += count[s * n_bins + e];
+  return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_part(const int* __restrict__ count, int S, int n_bins,
+                                                            int ca, int* __restrict__ part) {
+  __shared__ int wsum[2 * (kScanThreads / 64) + 1];
+  const bool bin_major = (int)blockIdx.x >= ca;
+  const int c = bin_major ? (int)blockIdx.x - ca : (int)blockIdx.x;
+  const int len = bin_major ? n_bins : S * n_bins;
+  int sum = 0;
 #pragma unroll
-      for (int s = 0; s < kMaxSpecies; ++s)
-        if (s < S && b < n_bins) t += count[s * n_bins + b];
-      buf[scan_pad<PER>(i)] = t;
-    }
-    __syncthreads();
-    scan_chunk<PER>(buf, wsum, &carry);
+  for (int u = 0; u < kScanPartPer; ++u) {
+    const int e = c * kScanPartChunk + u * kScanThreads + threadIdx.x;
+    if (e < len) sum += scan_entry(count, bin_major, e, S, n_bins);
+  }
+  int total;
+  block_exclusive(sum, wsum, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_fin(const int* __restrict__ count, int* __restrict__ start,
+                                                           int* __restrict__ cmstart, int S, int n_bins, int ca,
+                                                           const int* __restrict__ part) {
+  __shared__ int wsum[2 * (kScanThreads / 64) + 1];
+  __shared__ int buf[scan_lds_words<kScanPartPer>()];
+  __shared__ int s_carry;
+  const bool bin_major = (int)blockIdx.x >= ca;
+  const int c = bin_major ? (int)blockIdx.x - ca : (int)blockIdx.x;
+  const int first = bin_major ? ca : 0;
+  const int nb = S * n_bins, len = bin_major ? n_bins : nb;
+  if (threadIdx.x < 64) {   // the earlier chunks of this order
+    int v = 0;
+    for (int k = first + (int)threadIdx.x; k < (int)blockIdx.x; k += 64) v += part[k];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * kScanThreads + threadIdx.x, b = c0 + i;
-      if (b < n_bins) {
-        int r = buf[scan_pad<PER>(i)];
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x == 0) s_carry = v;
+  }
+  const int c0 = c * kScanPartChunk;
+#pragma unroll
+  for (int u = 0; u < kScanPartPer; ++u) {
+    const int i = u * kScanThreads + threadIdx.x;
+    buf[scan_pad<kScanPartPer>(i)] = c0 + i < len ? scan_entry(count, bin_major, c0 + i, S, n_bins) : 0;
+  }
+  __syncthreads();
+  int carry = s_carry;
+  scan_chunk<kScanPartPer>(buf, wsum, &carry);
+#pragma unroll
+  for (int u = 0; u < kScanPartPer; ++u) {
+    const int i = u * kScanThreads + threadIdx.x, e = c0 + i;
+    if (e < len) {
+      int r = buf[scan_pad<kScanPartPer>(i)];
+      if (bin_major) {
 #pragma unroll
         for (int s = 0; s < kMaxSpecies; ++s)
           if (s < S) {
-            cmstart[b * S + s] = r;
-            r += count[s * n_bins + b];
+            cmstart[e * S + s] = r;
+            r += count[s * n_bins + e];
           }
+      } else {
+        start[e] = r;
       }
     }
-    __syncthreads();
   }
-  // species-major
-  carry = 0;
-  for (int c0 = 0; c0 < nb; c0 += kScanThreads * PER) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * kScanThreads + threadIdx.x;
-      buf[scan_pad<PER>(i)] = c0 + i < nb ? count[c0 + i] : 0;
-    }
-    __syncthreads();
-    scan_chunk<PER>(buf, wsum, &carry);
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * kScanThreads + threadIdx.x;
-      if (c0 + i < nb) start[c0 + i] = buf[scan_pad<PER>(i)];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) start[nb] = carry;
+  if (!bin_major && c0 + kScanPartChunk >= len && threadIdx.x == 0) start[nb] = carry;
 }
 
 // Provisional slots: start of the key plus the atom's arrival rank.
@@ -1054,6 +1089,16 @@ inline int scan_entries_per_thread(int nb) {
 
 template <int PER>
 void launch_scan(nnp_model& m, hipStream_t st) {
+  const int nb = m.S * m.geo.n_bins;
+  if (nb > kScanChunk) {   // many workgroups
+    const int ca = (nb + kScanPartChunk - 1) / kScanPartChunk;
+    const int cb = (m.geo.n_bins + kScanPartChunk - 1) / kScanPartChunk;
+    hipLaunchKernelGGL(k_scan_part, dim3(ca + cb), dim3(kScanThreads), 0, st, m.d_bin_count, m.S, m.geo.n_bins, ca,
+                       m.d_scan_part);
+    hipLaunchKernelGGL(k_scan_fin, dim3(ca + cb), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start,
+                       m.d_cmstart, m.S, m.geo.n_bins, ca, m.d_scan_part);
+    return;
+  }
   hipLaunchKernelGGL(k_scan<PER>, dim3(1), dim3(kScanThreads), 0, st, m.d_bin_count, m.d_bin_start, m.d_cmstart,
                      m.S, m.geo.n_bins);
 }

@@ -229,6 +229,7 @@ struct Workspace {
   int* d_bin_count = nullptr;
   int* d_bin_start = nullptr;  // [max_bins + 1]
   int* d_cmstart = nullptr;    // [max_bins] bin-major starts (bin * S + species)
+  int* d_scan_part = nullptr;  // chunk totals of the many-workgroup histogram scan
   int* d_order = nullptr;      // [max_atoms] slots in bin-major visiting order
   int* d_perm = nullptr;       // slot -> NNP-local atom
   int* d_tmp = nullptr;        // scatter order before the in-bin ranking
@@ -338,6 +339,9 @@ int adjoint_variant(const nnp_model& m, int n);
 // else the tuned choice for this size; -1 means the stage's default.
 int stage_variant(const nnp_model& m, int stage, int n);
 constexpr int kStageVariants[kTuneStages] = {4, 5, 10, 3};
+// Histograms of more than this many entries are scanned by many workgroups
+// (chunk totals, then each chunk with the sum of the earlier ones).
+constexpr int kScanPartChunk = 4096;
 int size_bucket(int n);
 
 // workspace (api.cpp): capacities for a call of up to max_atoms atoms, and the

@@ -123,7 +123,7 @@ def test_cells_and_neighbours_bit_exact_full_size(P, name):
 
 def test_cells_and_neighbours_bit_exact_multichunk_scan(P):
     """3,087 waters in a 110 A box: 21^3 cells x 2 species = 18,522 bins, more than one
-    16,384-entry scan chunk, so the histogram takes the multi-chunk scan and the
+    16,384-entry scan chunk, so the histogram takes the many-workgroup scan and the
     separate scatter (the path of the 261,000-atom box) at a size checked in full."""
     pos, Z, box = sy.water_box(3087, 110.0, seed=4)
     m = P.NNPModel(WATER, weights=sy.flat_weights(sy.model_weights(WATER, seed=1)), precision="fp32")
@@ -188,3 +188,30 @@ def test_hcno_batch_256_full(P):
             print(f"hcno batch: bf16 rel rmse {rel_rmse(F, Fref):.3e}, worst atom {wa:.3e}")
             assert wa < BF16_ATOM_BOUND
         m.close()
+
+
+def test_batch_many_systems_scan(P):
+    """4,200 open H/C/N/O molecules of 2-4 atoms in one batched call: 4,200 systems x 4
+    species = 16,800 bins, so the batch's histogram also takes the many-workgroup scan.
+    Energies and forces of 120 sampled molecules against the oracle."""
+    w = sy.model_weights(HCNO, seed=1)
+    pos, Z, off = sy.walk_batch(4200, seed=5, nmin=2, nmax=4)
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w), precision="fp32")
+    E, F = m.compute_batch(torch.from_numpy(pos).cuda(), Z, off)
+    torch.cuda.synchronize()
+    assert m.status() == 0
+    E, F = E.cpu().numpy(), F.cpu().numpy()
+    pick = np.random.default_rng(2).choice(4200, size=120, replace=False)
+    sub_pos, sub_Z, sub_off, rows = [], [], [0], []
+    for s in np.sort(pick):
+        a, b = off[s], off[s + 1]
+        sub_pos.append(pos[a:b])
+        sub_Z.append(Z[a:b])
+        sub_off.append(sub_off[-1] + b - a)
+        rows.append(np.arange(a, b))
+    Eref, Fref = orc.evaluate_batch(np.concatenate(sub_pos), np.concatenate(sub_Z),
+                                    np.asarray(sub_off, dtype=np.int32), HCNO, w)
+    n = np.diff(sub_off)
+    assert np.all(np.abs(E[np.sort(pick)] - Eref) / n < 1e-6)
+    assert rel_rmse(F[np.concatenate(rows)], Fref) < 1e-5
+    m.close()
