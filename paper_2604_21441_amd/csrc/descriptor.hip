@@ -1131,11 +1131,14 @@ __global__ __launch_bounds__(kBlock) void k_force_gather(const float3* __restric
                                                          int max_rad, double* __restrict__ forces,
                                                          double* __restrict__ link_forces, int assign,
                                                          int gather_blocks, EnergyArgs ea) {
-  if ((int)blockIdx.x >= gather_blocks) {
-    energy_block(ea, (int)blockIdx.x - gather_blocks);
+  // the energy blocks come first, so that their serial reduction runs beside
+  // the gather instead of after it
+  const int energy_blocks = (int)gridDim.x - gather_blocks;
+  if ((int)blockIdx.x < energy_blocks) {
+    energy_block(ea, (int)blockIdx.x);
     return;
   }
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = ((int)blockIdx.x - energy_blocks) * blockDim.x + threadIdx.x;
   const int i = gid >> 4;
   const int sub = gid & 15;
   double fx = 0.0, fy = 0.0, fz = 0.0;
