@@ -11,6 +11,8 @@
 // the neighbour sets bit for bit.
 #include <algorithm>
 
+#include <cmath>
+
 #include "nnp_internal.h"
 
 namespace nnp {
@@ -600,6 +602,7 @@ struct NeighArgs {
   const int* bin_start;
   int n, S;
   float rc2, rca2;
+  float cull2;             // (sqrt(rc2) + kCullMargin)^2: stencil cells beyond it hold no neighbour
   int* rad;
   int* ang;
   int* angpos;
@@ -681,8 +684,7 @@ __global__ __launch_bounds__(64) void k_neighbours(NeighArgs a, Geometry g) {
       gap2 += gap * gap;
     }
     my_cell = (v[0] * g.nc[1] + v[1]) * g.nc[2] + v[2];
-    const float rm = sqrtf(a.rc2) + kCullMargin;
-    culled = gap2 > rm * rm;
+    culled = gap2 > a.cull2;
   }
 
   int* rad = a.rad + (int64_t)i * a.max_rad;
@@ -1194,6 +1196,10 @@ hipError_t launch_neighbours(nnp_model& m, int n, hipStream_t st) {
   a.S = m.S;
   a.rc2 = m.dp.rc_rad * m.dp.rc_rad;
   a.rca2 = m.dp.rc_ang * m.dp.rc_ang;
+  {
+    const float rm = std::sqrt(a.rc2) + kCullMargin;
+    a.cull2 = rm * rm;
+  }
   a.rad = m.d_nbr_rad;
   a.ang = m.d_nbr_ang;
   a.angpos = m.d_angpos;
@@ -1237,6 +1243,10 @@ hipError_t launch_pair_lists(nnp_model& m, int n, int n_atoms, int n_pairs, cons
   a.S = m.S;
   a.rc2 = m.dp.rc_rad * m.dp.rc_rad;
   a.rca2 = m.dp.rc_ang * m.dp.rc_ang;
+  {
+    const float rm = std::sqrt(a.rc2) + kCullMargin;
+    a.cull2 = rm * rm;
+  }
   a.rad = m.d_nbr_rad;
   a.ang = m.d_nbr_ang;
   a.angpos = m.d_angpos;
