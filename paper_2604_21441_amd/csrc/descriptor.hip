@@ -4,9 +4,10 @@
 // models the paper runs and benchmarks (Methods; performance section); the
 // adjoint gives F = -grad E (Theory, eq. 2).
 //
-// The forward runs one 16-lane row per atom (k_desc_fwd_rows, default) or one
-// wavefront per atom (k_desc_fwd); the adjoint one wavefront (or half of one)
-// per atom.  An output block is either the radial block of one neighbour
+// The forward runs one 16-lane row per atom (k_desc_fwd_rows, default), one
+// wavefront per atom (k_desc_fwd), or several atoms per wavefront with the
+// lanes balanced over chunks of all their work (k_desc_fwd_pool, for many
+// elements); the adjoint one wavefront (or half of one) per atom.  An output block is either the radial block of one neighbour
 // species (16 outputs) or the angular block of one unordered species pair
 // (8 x 4 outputs).
 //
