@@ -97,15 +97,24 @@ def log(*a):
 
 def kernel_sources():
     """Kernel base name -> defining source file and a digest of that file, the shared
-    header and the build script (a profile's counters are stale once these change)."""
+    header and the build script (a profile's counters are stale once these change).
+    Comments are left out of the digest: editing them changes no kernel."""
     import glob
     import hashlib
     import re
-    common = b"".join(open(f, "rb").read() for f in (os.path.join(CSRC, "nnp_internal.h"),
-                                                     os.path.join(ROOT, "paper_2604_21441_amd", "build.py")))
+
+    def code(path):
+        text = open(path, "rb").read()
+        if path.endswith((".hip", ".h")):
+            text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+            text = re.sub(rb"//[^\n]*", b"", text)
+        return text
+
+    common = b"".join(code(f) for f in (os.path.join(CSRC, "nnp_internal.h"),
+                                        os.path.join(ROOT, "paper_2604_21441_amd", "build.py")))
     out = {}
     for f in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
-        src = open(f, "rb").read()
+        src = code(f)
         dig = hashlib.sha256(src + common).hexdigest()[:16]
         for m in re.finditer(rb"__global__\s+(?:__launch_bounds__\([^)]*\)\s+)?void\s+(k_\w+)\s*\(", src):
             out[m.group(1).decode()] = {"file": os.path.basename(f), "digest": dig}
