@@ -139,29 +139,35 @@ def test_cells_and_neighbours_bit_exact_multichunk_scan(P):
 
 @pytest.mark.parametrize("name", list(SIZES))
 def test_energy_forces_full_size(P, name):
-    """Every atom's force and the energy against the FP64 oracle, both forms."""
+    """Every atom's force and the energy against the FP64 oracle, both forms, with the
+    default kernels and again with the kernels the autotuner picks (the launch
+    configuration the benchmark times)."""
     pos, Z, box = water(name)
     ref = oracle_water(name)
     n = len(Z)
     flat = sy.flat_weights(sy.model_weights(WATER, seed=1))
-    res = {}
+    d = torch.from_numpy(pos).cuda()
     for prec in ("fp32", "bf16"):
         m = P.NNPModel(WATER, weights=flat, precision=prec)
-        E, F, _ = m.compute(torch.from_numpy(pos).cuda(), Z, box)
-        torch.cuda.synchronize()
-        assert m.status() == 0
-        res[prec] = (E.item(), F.cpu().numpy())
+        for tuned in (False, True):
+            if tuned:
+                chosen = m.autotune(3)
+            E, F, _ = m.compute(d, Z, box)
+            torch.cuda.synchronize()
+            assert m.status() == 0
+            E, F = E.item(), F.cpu().numpy()
+            label = f"{name} {prec} {'tuned ' + str(chosen) if tuned else 'default'}"
+            if prec == "fp32":
+                assert abs(E - ref["E"]) / n < 1e-6, label
+                assert rel_rmse(F, ref["F"]) < 1e-5, label
+                print(f"{label}: rel rmse {rel_rmse(F, ref['F']):.3e}, worst atom {worst_atom(F, ref['F']):.3e}")
+            else:
+                assert abs(E - ref["E"]) / n < 2e-3, label
+                assert rel_rmse(F, ref["F"]) < 1e-2, label
+                wa = worst_atom(F, ref["F"])
+                print(f"{label}: rel rmse {rel_rmse(F, ref['F']):.3e}, worst atom {wa:.3e}")
+                assert wa < BF16_ATOM_BOUND, label
         m.close()
-    E32, F32 = res["fp32"]
-    assert abs(E32 - ref["E"]) / n < 1e-6
-    assert rel_rmse(F32, ref["F"]) < 1e-5
-    E16, F16 = res["bf16"]
-    assert abs(E16 - ref["E"]) / n < 2e-3
-    assert rel_rmse(F16, ref["F"]) < 1e-2
-    wa = worst_atom(F16, ref["F"])
-    print(f"{name}: bf16 rel rmse {rel_rmse(F16, ref['F']):.3e}, worst atom {wa:.3e}, "
-          f"fp32 rel rmse {rel_rmse(F32, ref['F']):.3e}, fp32 worst atom {worst_atom(F32, ref['F']):.3e}")
-    assert wa < BF16_ATOM_BOUND
 
 
 def test_hcno_batch_256_full(P):
@@ -171,22 +177,27 @@ def test_hcno_batch_256_full(P):
     pos, Z, off = sy.walk_batch(256, seed=0)
     Eref, Fref = orc.evaluate_batch(pos, Z, off, HCNO, w)
     sizes = np.diff(off)
+    d = torch.from_numpy(pos).cuda()
     for prec in ("fp32", "bf16"):
         m = P.NNPModel(HCNO, weights=sy.flat_weights(w), precision=prec)
-        E, F = m.compute_batch(torch.from_numpy(pos).cuda(), Z, off)
-        torch.cuda.synchronize()
-        assert m.status() == 0
-        E, F = E.cpu().numpy(), F.cpu().numpy()
-        de = np.abs(E - Eref) / sizes
-        if prec == "fp32":
-            assert de.max() < 1e-6
-            assert rel_rmse(F, Fref) < 1e-5
-        else:
-            assert de.max() < 2e-3
-            assert rel_rmse(F, Fref) < 1e-2
-            wa = worst_atom(F, Fref)
-            print(f"hcno batch: bf16 rel rmse {rel_rmse(F, Fref):.3e}, worst atom {wa:.3e}")
-            assert wa < BF16_ATOM_BOUND
+        for tuned in (False, True):
+            if tuned:
+                chosen = m.autotune(3)
+            E, F = m.compute_batch(d, Z, off)
+            torch.cuda.synchronize()
+            assert m.status() == 0
+            E, F = E.cpu().numpy(), F.cpu().numpy()
+            de = np.abs(E - Eref) / sizes
+            label = f"hcno batch {prec} {'tuned ' + str(chosen) if tuned else 'default'}"
+            if prec == "fp32":
+                assert de.max() < 1e-6, label
+                assert rel_rmse(F, Fref) < 1e-5, label
+            else:
+                assert de.max() < 2e-3, label
+                assert rel_rmse(F, Fref) < 1e-2, label
+                wa = worst_atom(F, Fref)
+                print(f"{label}: rel rmse {rel_rmse(F, Fref):.3e}, worst atom {wa:.3e}")
+                assert wa < BF16_ATOM_BOUND, label
         m.close()
 
 
