@@ -446,14 +446,16 @@ __global__ __launch_bounds__(256) void k_desc_fwd_rows(FwdArgs a, DescParams p, 
 // chunk's block in registers.  The chunks of a unit then add up pairwise in
 // a tree (chunk c + d into chunk c for c a multiple of 2d, d = 1, 2, 4, ...,
 // 16 values at a time through LDS), and the unit's first chunk stores the
-// block in the descriptor row.  With
-// several elements a class holds few pairs (about 14 per class for H/C/N/O
-// molecules against 17 angular neighbours): the row kernels then leave most
-// lanes of a row idle and pay a 32-value cross-lane reduction per class,
-// which this kernel avoids.  Adding the partials with LDS float atomics
-// instead was several times slower.  The radial phase runs first, so that
-// the partial rows can share LDS with the angular geometry (each is dead
-// while the other is live).
+// block in the descriptor row.
+//
+// With several elements a class holds few pairs (about 14 per class for
+// H/C/N/O molecules against 17 angular neighbours): the row kernels then
+// leave most lanes of a row idle and pay a 32-value cross-lane reduction per
+// class, which this kernel avoids.  Adding the partials with LDS float
+// atomics instead was several times slower.  The radial phase runs first,
+// with the first pass of the angular geometry already loaded into registers,
+// so that the partial rows can share LDS with the angular geometry (each is
+// dead while the other is live).
 constexpr int kPoolPitch = 20;   // LDS row of one lane's 16 partial sums (16-byte aligned)
 
 // Inclusive prefix sum / maximum over the 64 lanes with DPP: row shifts
