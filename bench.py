@@ -98,7 +98,8 @@ def log(*a):
 def kernel_sources():
     """Kernel base name -> defining source file and a digest of that file, the shared
     header and the build script (a profile's counters are stale once these change).
-    Comments are left out of the digest: editing them changes no kernel."""
+    Comments and the layout of whitespace are left out of the digest: editing them
+    changes no kernel."""
     import glob
     import hashlib
     import re
@@ -108,6 +109,7 @@ def kernel_sources():
         if path.endswith((".hip", ".h")):
             text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
             text = re.sub(rb"//[^\n]*", b"", text)
+            text = re.sub(rb"\s+", b" ", text)
         return text
 
     common = b"".join(code(f) for f in (os.path.join(CSRC, "nnp_internal.h"),
