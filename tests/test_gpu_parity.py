@@ -708,6 +708,46 @@ def test_pool_descriptor_dense_and_isolated(P, w_hcno, variant):
     m.close()
 
 
+@pytest.fixture(scope="module")
+def hcno_periodic(w_hcno):
+    """420 H/C/N/O atoms at least 1 A apart (minimum image) in a periodic 14 A box:
+    about 27 angular neighbours per atom, pairs across every face."""
+    rng = np.random.default_rng(21)
+    L = 14.0
+    pts = []
+    while len(pts) < 420:
+        p = rng.uniform(0.0, L, 3)
+        if pts:
+            d = np.asarray(pts) - p
+            d -= L * np.round(d / L)
+            if np.min(np.einsum("ij,ij->i", d, d)) < 1.0:
+                continue
+        pts.append(p)
+    pos = np.asarray(pts, dtype=np.float32)
+    Z = rng.choice(np.array([1, 6, 7, 8], dtype=np.int32), size=len(pos))
+    box = np.array([L, L, L], dtype=np.float32)
+    return pos, Z, box, orc.evaluate(pos, Z, HCNO, w_hcno, box=box, return_x=True)
+
+
+@pytest.mark.parametrize("variant", [1, 3, 4])
+def test_descriptor_variants_hcno_periodic(P, w_hcno, hcno_periodic, variant):
+    """Row and pool descriptor kernels on a periodic H/C/N/O box (minimum image across the
+    faces, ten classes): descriptor rows, energy and forces against the oracle."""
+    pos, Z, box, ref = hcno_periodic
+    m = P.NNPModel(HCNO, weights=sy.flat_weights(w_hcno), precision="fp32")
+    m.set_variant("descriptor", variant)
+    E, F, _ = _run(m, pos, Z, box)
+    perm = m.read(P._lib.NNP_BUF_PERM)
+    x = m.read(P._lib.NNP_BUF_DESCRIPTOR)[:, :384]
+    xr = np.empty(x.shape)
+    xr[perm] = x
+    err = np.linalg.norm(xr - ref["x"], axis=1) / np.linalg.norm(ref["x"], axis=1)
+    assert err.max() < 5e-6, err.max()
+    assert abs(E[0] - ref["E"]) / len(Z) < 1e-6
+    assert rel_rmse(F, ref["F"]) < 1e-5
+    m.close()
+
+
 # ------------------------------------------------------------------ batching
 def test_batched_open_systems(P, w_hcno):
     pos, Z, off = sy.walk_batch(12, seed=4)
