@@ -89,6 +89,26 @@ def test_batched_periodic_boxes(P):
         m.close()
 
 
+@pytest.mark.parametrize("stage,variant", [("descriptor", 0), ("descriptor", 2), ("descriptor", 3),
+                                           ("descriptor", 4), ("adjoint", 1), ("adjoint", 2),
+                                           ("neighbours", 1)])
+def test_batched_periodic_boxes_variants(P, stage, variant):
+    """Every kernel variant that reads the per-system boxes, pinned, on the batch of
+    periodic boxes and an open cluster: energies and forces against the oracle."""
+    w = sy.model_weights(WATER, seed=1)
+    pos, Z, off, boxes = _water_batch()
+    Eref, Fref = orc.evaluate_batch(pos, Z, off, WATER, w, boxes=boxes)
+    m = P.NNPModel(WATER, weights=sy.flat_weights(w), precision="fp32")
+    m.set_variant(stage, variant)
+    E, F = m.compute_batch(torch.from_numpy(pos).cuda(), Z, off, boxes=boxes)
+    torch.cuda.synchronize()
+    assert m.status() == 0
+    E, F = E.cpu().numpy(), F.cpu().numpy()
+    assert np.all(np.abs(E - Eref) / np.diff(off) < 1e-6), (E, Eref)
+    assert rel_rmse(F, Fref) < 1e-5
+    m.close()
+
+
 def test_batched_boxes_change_between_replays(P):
     """New boxes (and positions) every call: uploaded to device memory, the captured graph
     is replayed unchanged, and each call matches the oracle for its own boxes."""
