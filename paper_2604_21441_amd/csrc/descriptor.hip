@@ -1102,11 +1102,26 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int sys) {
       const int rows = s == narrow ? 16 : ea.tile_rows;
       tiles += (ea.bin_start[(s + 1) * ea.n_bins] - ea.bin_start[s * ea.n_bins] + rows - 1) / rows;
     }
-    for (int t = threadIdx.x; t < tiles; t += kBlock) acc += ea.part[t];
+    // eight loads in flight per thread, added in the same order as one at a time
+    for (int t0 = threadIdx.x; t0 < tiles; t0 += 8 * kBlock) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = t0 + u * kBlock < tiles ? ea.part[t0 + u * kBlock] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (t0 + u * kBlock < tiles) acc += v[u];
+    }
   } else {
     for (int s = 0; s < ea.S; ++s) {
       const int b0 = ea.bin_start[s * ea.n_bins + sys], b1 = ea.bin_start[s * ea.n_bins + sys + 1];
-      for (int t = b0 + threadIdx.x; t < b1; t += kBlock) acc += (double)ea.e[t];
+      for (int t0 = b0 + threadIdx.x; t0 < b1; t0 += 8 * kBlock) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = t0 + u * kBlock < b1 ? ea.e[t0 + u * kBlock] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (t0 + u * kBlock < b1) acc += (double)v[u];
+      }
     }
   }
   red[threadIdx.x] = acc;
