@@ -861,16 +861,52 @@ __device__ __forceinline__ void chunk_to_frags(int r0, const v4f (*acc)[C], v8bf
       }
 }
 
-// CELU in the form the kernel evaluates it: t = 2^(u log2(e) / alpha), h = u
-// for u > 0, else alpha t - alpha; and its derivative from h: 1 for h > 0,
-// else h / alpha + 1 = min(h / alpha + 1, 1) (h / alpha + 1 > 1 exactly when
-// h > 0).
-__device__ __forceinline__ float celu_lean(float u, float alpha, float inv_alpha_l2) {
-  const float t = __builtin_amdgcn_exp2f(u * inv_alpha_l2);
-  return u > 0.f ? u : fmaf(alpha, t, -alpha);
+// CELU in the form the kernel evaluates it: t = 2^(u log2(e) / alpha) and
+// h = med3(u, alpha t - alpha, 0), since 0 < u < alpha (t - 1) for u > 0 and
+// u <= alpha (t - 1) <= 0 for u <= 0; its derivative is min(t, 1) (t > 1
+// exactly when u > 0), kept for the backward pass as packed FP16 (rounded
+// toward zero: relative error below 2^-10).
+__device__ __forceinline__ float celu_med3(float u, float t, float alpha) {
+  return __builtin_amdgcn_fmed3f(u, fmaf(alpha, t, -alpha), 0.f);
 }
+// celu' from the (BF16-rounded) activation h: 1 for h > 0, else h / alpha + 1
+// = min(h / alpha + 1, 1) (h / alpha + 1 > 1 exactly when h > 0).
 __device__ __forceinline__ float celu_grad_lean(float h, float inv_alpha) {
   return fminf(fmaf(h, inv_alpha, 1.f), 1.f);
+}
+__device__ __forceinline__ uint32_t celu_grad_pk(float t0, float t1) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fminf(t0, 1.f), fminf(t1, 1.f)));
+}
+// x times the FP16 value in the low (HI false) or high half of d, rounded
+// once.  Written as fma(x, d, +0) (which, unlike a product, the compiler may
+// not turn into a multiplication: the sign of a zero product differs), so that
+// it becomes one mixed-precision fma instead of a conversion and a product; the
+// compiler then also inserts the wait states after the matrix-core products
+// whose results it reads.
+template <bool HI>
+__device__ __forceinline__ float mul_f16(float x, uint32_t d) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  const h2 v = __builtin_bit_cast(h2, d);
+  return __builtin_fmaf(x, (float)v[HI ? 1 : 0], 0.f);
+}
+
+// The FP16 derivatives of accumulator tiles r0 .. r0 + CH - 1 in the element
+// order of chunk_to_frags: fragment rt / 2, dword 2 (rt % 2) + u / 2, half
+// u % 2 for feature 16 rt + 4 q + u.
+template <int R, int CH, int C>
+__device__ __forceinline__ void chunk_to_grads(int r0, const v4f (*t)[C], uint32_t (*d)[C][4]) {
+#pragma unroll
+  for (int r = 0; r < CH; r += 2)
+    if (r0 + r < R / 16)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        uint32_t* o = d[(r0 + r) / 2][c];
+        o[0] = celu_grad_pk(t[r][c][0], t[r][c][1]);
+        o[1] = celu_grad_pk(t[r][c][2], t[r][c][3]);
+        o[2] = celu_grad_pk(t[r + 1][c][0], t[r + 1][c][1]);
+        o[3] = celu_grad_pk(t[r + 1][c][2], t[r + 1][c][3]);
+        asm volatile("" : "+v"(o[0]), "+v"(o[1]), "+v"(o[2]), "+v"(o[3]));
+      }
 }
 
 template <int K0, int N1, int N2, int N3, int C, int NW>
@@ -970,7 +1006,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mlp_lds(MlpArgs a, float alpha) 
   const v4f zero = v4f{0.f, 0.f, 0.f, 0.f};
 
   const int waves = gs * NW;
-  for (int t = ((int)blockIdx.x - wg0) * NW + w; t < ts_mine; t += waves) {
+  // tile t = rank * gs + workgroup, rank = wavefront in its workgroup: every
+  // round of `waves` tiles gives each workgroup the same number, and a last,
+  // partial round gives its tiles to the low ranks of every workgroup, which
+  // fall on different SIMDs
+  for (int t = w * gs + ((int)blockIdx.x - wg0); t < ts_mine; t += waves) {
     const int row0 = b0_mine + t * TILE;
     // x as B fragments: column tile c, K block kb: atom row0 + 16 c + col,
     // features 32 kb + 4 q .. +3 and 32 kb + 16 + 4 q .. +3 (zero beyond the
@@ -1005,36 +1045,48 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mlp_lds(MlpArgs a, float alpha) 
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[r][c] = zero;
     };
-    auto celu_chunk = [&](v4f (*acc)[C]) {
+    // h = celu(u) in place, t = 2^(u log2(e) / alpha) beside it
+    auto celu_chunk = [&](v4f (*acc)[C], v4f (*t)[C]) {
 #pragma unroll
       for (int r = 0; r < CH; ++r)
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[r][c][u] = celu_lean(acc[r][c][u], alpha, inv_alpha_l2);
+          for (int u = 0; u < 4; ++u) {
+            t[r][c][u] = __builtin_amdgcn_exp2f(acc[r][c][u] * inv_alpha_l2);
+            acc[r][c][u] = celu_med3(acc[r][c][u], t[r][c][u], alpha);
+          }
     };
-    // celu'(h) o acc with h from the BF16 fragments of the forward pass
-    auto times_grad = [&](int r0, v4f (*acc)[C], const v8bf (*hf)[C], int R) {
+    // celu'(u) o acc with the FP16 derivatives of the forward pass
+    auto times_grad = [&](int r0, v4f (*acc)[C], const uint32_t (*gd)[C][4], int R) {
 #pragma unroll
       for (int r = 0; r < CH; ++r)
 #pragma unroll
         for (int c = 0; c < C; ++c)
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (r0 + r < R)
-              acc[r][c][u] *= celu_grad_lean((float)hf[(r0 + r) >> 1][c][4 * ((r0 + r) & 1) + u], inv_alpha);
+            if (r0 + r < R) {
+              const uint32_t d = gd[(r0 + r) >> 1][c][2 * ((r0 + r) & 1) + (u >> 1)];
+              acc[r][c][u] = (u & 1) ? mul_f16<true>(acc[r][c][u], d) : mul_f16<false>(acc[r][c][u], d);
+            }
     };
-    // ---- layer 1: h1 = celu(W1 x + b1)
+    // ---- layer 1: h1 = celu(W1 x + b1), and celu' for the backward pass
     v8bf h1f[N1 / 32][C];
+    uint32_t g1d[N1 / 32][C][4];
     lds_product<N1, K0, Lay::P1, false, CH, C>(W1, xf, lane, bias_init(vb1), [&](int r0, v4f (*acc)[C]) {
-      celu_chunk(acc);
+      v4f t[CH][C];
+      celu_chunk(acc, t);
       chunk_to_frags<N1, CH, C>(r0, acc, h1f);
+      chunk_to_grads<N1, CH, C>(r0, t, g1d);
     });
-    // ---- layer 2: h2 = celu(W2 h1 + b2)
+    // ---- layer 2: h2 = celu(W2 h1 + b2), and celu' for the backward pass
     v8bf h2f[N2 / 32][C];
+    uint32_t g2d[N2 / 32][C][4];
     lds_product<N2, N1, Lay::P2, false, CH, C>(W2, h1f, lane, bias_init(vb2), [&](int r0, v4f (*acc)[C]) {
-      celu_chunk(acc);
+      v4f t[CH][C];
+      celu_chunk(acc, t);
       chunk_to_frags<N2, CH, C>(r0, acc, h2f);
+      chunk_to_grads<N2, CH, C>(r0, t, g2d);
     });
     // ---- layer 3, the output, and delta3 = w4 o celu'(h3)
     v8bf d3f[N3 / 32][C];
@@ -1050,7 +1102,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mlp_lds(MlpArgs a, float alpha) 
         for (int c = 0; c < C; ++c)
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const float h = celu_lean(acc[r][c][u], alpha, inv_alpha_l2);
+            const float h = celu_med3(acc[r][c][u], __builtin_amdgcn_exp2f(acc[r][c][u] * inv_alpha_l2), alpha);
             ep[c] = fmaf(w4[u], h, ep[c]);
             acc[r][c][u] = w4[u] * celu_grad_lean(h, inv_alpha);
           }
@@ -1060,13 +1112,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_mlp_lds(MlpArgs a, float alpha) 
     // ---- delta2 = (W3^T delta3) o celu'(h2)
     v8bf d2f[N2 / 32][C];
     lds_product<N2, N3, Lay::P3, true, CH, C>(W3, d3f, lane, zero_init, [&](int r0, v4f (*acc)[C]) {
-      times_grad(r0, acc, h2f, N2 / 16);
+      times_grad(r0, acc, g2d, N2 / 16);
       chunk_to_frags<N2, CH, C>(r0, acc, d2f);
     });
     // ---- delta1 = (W2^T delta2) o celu'(h1)
     v8bf d1f[N1 / 32][C];
     lds_product<N1, N2, Lay::P2, true, CH, C>(W2, d2f, lane, zero_init, [&](int r0, v4f (*acc)[C]) {
-      times_grad(r0, acc, h1f, N1 / 16);
+      times_grad(r0, acc, g1d, N1 / 16);
       chunk_to_frags<N1, CH, C>(r0, acc, d1f);
     });
     // ---- dE/dx = W1^T delta1, to memory
