@@ -863,14 +863,17 @@ __device__ __forceinline__ void chunk_to_frags(int r0, const v4f (*acc)[C], v8bf
 
 // CELU in the form the kernel evaluates it: t = 2^(u log2(e) / alpha) and
 // h = med3(u, alpha t - alpha, 0), since 0 < u < alpha (t - 1) for u > 0 and
-// u <= alpha (t - 1) <= 0 for u <= 0; its derivative is min(t, 1) (t > 1
-// exactly when u > 0), kept for the backward pass as packed FP16 (rounded
-// toward zero: relative error below 2^-10).
+// u <= alpha (t - 1) <= 0 for u <= 0 (near u = 0, where rounding can swap
+// the order of the first two, either is returned; they then differ by about
+// alpha 2^-23); its derivative is min(t, 1) (t > 1 exactly when u > 0), kept
+// for the backward pass as packed FP16 (rounded toward zero: relative error
+// below 2^-10).
 __device__ __forceinline__ float celu_med3(float u, float t, float alpha) {
   return __builtin_amdgcn_fmed3f(u, fmaf(alpha, t, -alpha), 0.f);
 }
-// celu' from the (BF16-rounded) activation h: 1 for h > 0, else h / alpha + 1
-// = min(h / alpha + 1, 1) (h / alpha + 1 > 1 exactly when h > 0).
+// celu' from the activation h (the output layer's, in FP32): 1 for h > 0,
+// else h / alpha + 1 = min(h / alpha + 1, 1) (h / alpha + 1 > 1 exactly when
+// h > 0).
 __device__ __forceinline__ float celu_grad_lean(float h, float inv_alpha) {
   return fminf(fmaf(h, inv_alpha, 1.f), 1.f);
 }
@@ -878,11 +881,11 @@ __device__ __forceinline__ uint32_t celu_grad_pk(float t0, float t1) {
   return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(fminf(t0, 1.f), fminf(t1, 1.f)));
 }
 // x times the FP16 value in the low (HI false) or high half of d, rounded
-// once.  Written as fma(x, d, +0) (which, unlike a product, the compiler may
-// not turn into a multiplication: the sign of a zero product differs), so that
-// it becomes one mixed-precision fma instead of a conversion and a product; the
-// compiler then also inserts the wait states after the matrix-core products
-// whose results it reads.
+// once.  It is written as fma(x, d, +0), which the compiler must keep as an
+// fma (a zero product's sign can differ from the fma's) and emits as one
+// mixed-precision fma instead of a conversion and a product, inserting
+// itself the wait states after the matrix-core products whose results it
+// reads.
 template <bool HI>
 __device__ __forceinline__ float mul_f16(float x, uint32_t d) {
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));

@@ -417,8 +417,8 @@ def test_lds_network_kernel(P, w_water, boxes, oracle_res):
     BF16 kernel, and against variant 2 within BF16 rounding: the CELU is one fma and a
     median and the output-layer dot product is summed in another order (FP32 rounding,
     which can move a BF16-rounded activation by one BF16 ulp), and celu' comes from
-    min(exp(u / alpha), 1) kept in FP16 (hidden layers, relative 2^-10) or from the
-    BF16-rounded activation (output layer, 2^-9)."""
+    min(exp(u / alpha), 1) kept in FP16 for the hidden layers (relative 2^-10), where
+    variant 2 computes it in FP32 from the FP32 activation."""
     for name in ("c1", "c2"):
         pos, Z, box = boxes[name]
         out = {}
@@ -440,7 +440,7 @@ def test_lds_network_kernel(P, w_water, boxes, oracle_res):
             de = np.abs(out[v][2] - out[2][2])
             assert de.max() < 5e-4, (name, v, de.max())                      # atomic energies
             assert abs(out[v][0][0] - out[2][0][0]) / len(Z) < 1e-5, (name, v)
-            # celu' differs by at most 2^-9 per element (FP16 derivative or BF16 h);
+            # celu' differs by at most 2^-10 relative per element (FP16 derivative);
             # three backward layers: a few 1e-3 relative
             assert rel_rmse(out[v][3], out[2][3]) < 5e-3, (name, v)          # dE/dx
             assert rel_rmse(out[v][1], out[2][1]) < 5e-3, (name, v)          # forces
